@@ -1,0 +1,165 @@
+"""CPU oracle for the checkerboard Metropolis Ising sweep -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package.  The GPU library never imports it.  It wraps the plain C
+implementation in ``ising_oracle.c`` (one byte per spin, its own
+Philox4x32-10) with numpy arrays; see that file for the definitions and the
+passages of the paper each function follows.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libising_oracle.so")
+_lib = None
+
+COLD = 0
+HOT = 1
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build  # build only if nothing is built yet
+        _build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    i32, u32, u64, i64, dbl = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_double
+    lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_word_rows.argtypes = [i32]
+    lib.oracle_word_rows.restype = i32
+    lib.oracle_site_uniform.argtypes = [u64, u32, u64, i32, i32, i32]
+    lib.oracle_site_uniform.restype = u32
+    lib.oracle_thresholds.argtypes = [dbl, u32p, u32p]
+    lib.oracle_thresholds.restype = None
+    lib.oracle_accept.argtypes = [ctypes.c_int, u32, u32, u32]
+    lib.oracle_accept.restype = ctypes.c_int
+    lib.oracle_init.argtypes = [i32, u64, i32, u8p]
+    lib.oracle_init.restype = ctypes.c_int
+    lib.oracle_observables.argtypes = [i32, u8p, i64p, i64p]
+    lib.oracle_observables.restype = None
+    lib.oracle_sweep_measure.argtypes = [i32, u64, u64, i64, dbl, u8p, i32, i64p, i64p, i32]
+    lib.oracle_sweep_measure.restype = ctypes.c_int
+    lib.oracle_sweep.argtypes = [i32, u64, u64, i64, dbl, u8p, i32]
+    lib.oracle_sweep.restype = ctypes.c_int
+    lib.oracle_max_threads.argtypes = []
+    lib.oracle_max_threads.restype = i32
+    lib.oracle_init_window.argtypes = [i32, u64, i32, i32, i32, i32, i32, u8p]
+    lib.oracle_init_window.restype = ctypes.c_int
+    lib.oracle_sweep_window.argtypes = [i32, u64, u64, i64, dbl, i32, i32, i32, i32, u8p, i32]
+    lib.oracle_sweep_window.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _u8(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _i64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block: 4 counter words, 2 key words -> 4 output words."""
+    lib = _load()
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib.oracle_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def word_rows(L):
+    return int(_load().oracle_word_rows(int(L)))
+
+
+def site_uniform(seed, stream, t, L, r, c):
+    return int(_load().oracle_site_uniform(int(seed), int(stream), int(t), int(L), int(r), int(c)))
+
+
+def thresholds(T):
+    """(t4, t8) = floor(exp(-4/T) 2^32), floor(exp(-8/T) 2^32), clamped."""
+    t4 = ctypes.c_uint32()
+    t8 = ctypes.c_uint32()
+    _load().oracle_thresholds(float(T), ctypes.byref(t4), ctypes.byref(t8))
+    return int(t4.value), int(t8.value)
+
+
+def accept(n_anti, u, t4, t8):
+    return bool(_load().oracle_accept(int(n_anti), int(u), int(t4), int(t8)))
+
+
+def max_threads():
+    return int(_load().oracle_max_threads())
+
+
+def init(L, seed, hot):
+    """Initial state, uint8 array (L, L): 1 = up, 0 = down."""
+    s = np.empty((L, L), dtype=np.uint8)
+    if _load().oracle_init(int(L), int(seed), int(bool(hot)), _u8(s)) != 0:
+        raise ValueError(f"invalid lattice size L={L}")
+    return s
+
+
+def observables(s):
+    """Exact (E, M) of a uint8 (L, L) state: E = -sum of right+down bonds."""
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    E = ctypes.c_int64()
+    M = ctypes.c_int64()
+    _load().oracle_observables(int(s.shape[0]), _u8(s), ctypes.byref(E), ctypes.byref(M))
+    return int(E.value), int(M.value)
+
+
+def sweep(s, seed, t0, n_sweeps, T, every=0, threads=0):
+    """Advance state ``s`` (modified in place) by n_sweeps sweeps at T.
+
+    Sweep indices are absolute: the first sweep performed is t0.  With
+    ``every > 0`` returns (E_series, M_series) sampled after every
+    ``every``-th sweep of this call; otherwise returns None.
+    """
+    assert s.dtype == np.uint8 and s.flags.c_contiguous and s.shape[0] == s.shape[1]
+    L = s.shape[0]
+    n = int(n_sweeps)
+    if every > 0:
+        k = n // every
+        Es = np.zeros(k, dtype=np.int64)
+        Ms = np.zeros(k, dtype=np.int64)
+        rc = _load().oracle_sweep_measure(L, int(seed), int(t0), n, float(T), _u8(s), int(every),
+                                          _i64(Es), _i64(Ms), int(threads))
+        if rc != 0:
+            raise ValueError("bad sweep arguments")
+        return Es, Ms
+    rc = _load().oracle_sweep(L, int(seed), int(t0), n, float(T), _u8(s), int(threads))
+    if rc != 0:
+        raise ValueError("bad sweep arguments")
+    return None
+
+
+def init_window(L, seed, hot, r0, c0, h, w):
+    win = np.empty((h, w), dtype=np.uint8)
+    if _load().oracle_init_window(int(L), int(seed), int(bool(hot)), int(r0), int(c0), int(h), int(w),
+                                  _u8(win)) != 0:
+        raise ValueError("bad window")
+    return win
+
+
+def sweep_window(win, L, seed, t0, n_sweeps, T, r0, c0, threads=0):
+    """Evolve a window in place; exact on [2n, h-2n) x [2n, w-2n) afterwards."""
+    assert win.dtype == np.uint8 and win.flags.c_contiguous
+    h, w = win.shape
+    rc = _load().oracle_sweep_window(int(L), int(seed), int(t0), int(n_sweeps), float(T), int(r0), int(c0),
+                                     int(h), int(w), _u8(win), int(threads))
+    if rc != 0:
+        raise ValueError("bad window sweep")
