@@ -1,0 +1,276 @@
+/*
+ * ising.h -- C ABI of the MI355X (gfx950) multi-spin-coded Ising library.
+ *
+ * The library runs the checkerboard Metropolis sweep of the 2D square-lattice
+ * Ising model with periodic boundaries, J = 1, h = 0, k_B = 1
+ * (Hamiltonian: Section 2, Eq. 1; acceptance rule: Section 2, steps 1-3),
+ * on lattices stored with the paper's multi-spin coding: 21 spins of 3 bits
+ * in each 64-bit word, bit 63 always 0, "001" = up and "000" = down
+ * (Section 3), word row I of column J holding the spins of rows
+ * I, I+N, ..., I+20N (Section 3, Fig. 1), with the periodic wrap between the
+ * first and last word rows made by 3-bit shifts (Section 3, Fig. 2).  The
+ * neighbour count is the XOR sum of Eq. 3 and its meaning is Table 1 of
+ * Section 3.1.  Energies are computed from right and down bonds, each bond
+ * once (Section 5.3, Listing 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - L: linear size, even, 4 <= L <= 262144 (2^18).  The lattice has L*L
+ *    spins.  The word lattice has N(L) rows and L columns, N(L) the smallest
+ *    even integer >= L/21; rows r >= L of the 21*N(L) coded rows are dead
+ *    slots (always 0, never flipped, not counted).  For L = 21N with N even
+ *    this is exactly the paper's layout.
+ *  - Word layout in device memory: uint64 W[N][L], row major (column index
+ *    fastest); the spin of row r, column c is bit 3*(20 - r/N) of W[r%N][c].
+ *  - T: temperature in units of J/k_B, finite and > 0.  The acceptance
+ *    thresholds t4 = floor(exp(-4/T) 2^32) and t8 = floor(exp(-8/T) 2^32)
+ *    (clamped to 2^32-1) are computed on the host in IEEE double; a move with
+ *    dE = +4J (+8J) is accepted iff its 32-bit uniform u < t4 (u < t8), moves
+ *    with dE <= 0 always.
+ *  - Random numbers: Philox4x32-10 keyed by the 64-bit seed
+ *    (key = (seed mod 2^32, seed div 2^32)).  Site (r, c) at absolute sweep t
+ *    uses counter (t mod 2^32, I*L + c', t div 2^32, g + 8*stream) and output
+ *    word q, with I = r mod N, p = r div N and
+ *      p < 20:  g = p div 4, q = p mod 4, c' = c;
+ *      p = 20:  g = 5, q = (c div 2) mod 4, c' = 8*(c div 8) + (c mod 2);
+ *    stream 0 is the hot-start draw (t = 0), stream 1 the Metropolis sweeps.
+ *    A hot start sets a site up iff its draw is < 2^31; a cold start sets all
+ *    spins up.
+ *  - Sweep t: all sites with (r + c) even are updated, then all with
+ *    (r + c) odd.  Sweep indices are absolute per lattice: sweeping a then b
+ *    equals sweeping a + b, and the temperature may change between calls.
+ *  - E = -sum over bonds of s_i s_j (each bond once), M = sum of s_i, both
+ *    exact int64 in units of J (resp. spins).
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls that only enqueue device work return before it runs;
+ *    only the calls documented as synchronising wait for the stream.
+ *  - Memory: "device pointer" means memory the GPU can address (hipMalloc or
+ *    a torch CUDA tensor); "host pointer" means ordinary process memory.
+ *    The library never frees memory it did not allocate.
+ *  - Errors: every int-returning call returns ISING_OK (0) or a negative
+ *    ISING_E* code and then leaves a message for ising_last_error() in
+ *    thread-local storage.  No C++ exception crosses this interface.
+ *  - Threading: one handle must not be used by two threads at once; distinct
+ *    handles are independent.
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ISING_OK = 0,
+    ISING_EINVAL = -1, /* argument out of range (L, T, sweeps, pointers, sizes)      */
+    ISING_ENOMEM = -2, /* device allocation failed or a memory budget is exceeded    */
+    ISING_EHIP = -3,   /* a HIP runtime call failed (message names it)               */
+    ISING_EBUSY = -4,  /* the object is in a state that forbids the call             */
+    ISING_EAGAIN = -5  /* nothing available yet (server queue)                       */
+};
+enum { ISING_COLD = 0, ISING_HOT = 1 };
+
+typedef struct ising_lattice ising_lattice; /* one lattice (opaque)                 */
+typedef struct ising_batch ising_batch;     /* many lattices, one launch per phase  */
+typedef struct ising_server ising_server;   /* continuous-batching request server   */
+
+/* ------------------------------------------------------------------ */
+/* Geometry and thresholds (host only, no GPU needed)                   */
+/* ------------------------------------------------------------------ */
+
+/* N(L), the number of word rows (Section 3 with the even-N reading for
+   L not a multiple of 21); 0 if L is invalid. */
+int32_t ising_word_rows(int32_t L);
+
+/* Bytes of the packed word lattice, 8 * N(L) * L; 0 if L is invalid. */
+size_t ising_required_bytes(int32_t L);
+
+/* Acceptance thresholds for temperature T (Section 2, step 3, with dE from
+   Table 1).  EINVAL if T is not finite and > 0. */
+int ising_thresholds(double T, uint32_t* t4, uint32_t* t8);
+
+/* Library version string and the GPU architecture it was built for. */
+const char* ising_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ising_last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* Single lattice: one lattice per kernel launch                        */
+/* ------------------------------------------------------------------ */
+
+/* Allocate (hipMalloc) and initialise a lattice: init = ISING_COLD or
+   ISING_HOT (Section 5.1 initialises at random; the hot start is that).
+   The initialisation kernel is enqueued on `stream`.  *out receives the
+   handle; the library owns it and its device memory. */
+int ising_create(int32_t L, uint64_t seed, int32_t init, void* stream, ising_lattice** out);
+
+/* As ising_create, but the word lattice lives in a caller-owned device
+   buffer `dev_words` of `bytes` >= ising_required_bytes(L) bytes, 8-byte
+   aligned, which must outlive the handle (e.g. a torch CUDA tensor). */
+int ising_create_in(int32_t L, uint64_t seed, int32_t init, void* dev_words, size_t bytes, void* stream,
+                    ising_lattice** out);
+
+/* Release the handle (and the device memory the library allocated).
+   Waits for the handle's stream first.  NULL is accepted. */
+int ising_destroy(ising_lattice* h);
+
+/* Enqueue n_sweeps >= 0 checkerboard sweeps at temperature T. */
+int ising_sweep(ising_lattice* h, double T, int64_t n_sweeps);
+
+/* As ising_sweep, and after the k-th sweep of this call (k = every, 2 every,
+   ...) store that state's E and M in dev_E[k/every - 1] and dev_M[k/every - 1]
+   (device pointers to n_sweeps/every int64 each).  The reduction is fused
+   into the second half of the sampled sweep.  every >= 1. */
+int ising_sweep_measure(ising_lattice* h, double T, int64_t n_sweeps, int32_t every, int64_t* dev_E,
+                        int64_t* dev_M);
+
+/* E and M of the current state (host pointers).  Synchronises the stream. */
+int ising_observables(ising_lattice* h, int64_t* E, int64_t* M);
+
+/* Copy the spins to a host array of L*L bytes, row major, 1 = up, 0 = down.
+   Synchronises the stream. */
+int ising_get_spins(ising_lattice* h, uint8_t* host_spins);
+
+/* Spins of the h x w window with top-left site (r0, c0), indices taken
+   modulo L, into a host array of h*w bytes.  1 <= h, w <= L.  Synchronises. */
+int ising_get_spins_region(ising_lattice* h, int32_t r0, int32_t c0, int32_t nrows, int32_t ncols,
+                           uint8_t* host_spins);
+
+/* Replace the state by a host array of L*L bytes (nonzero = up).  The sweep
+   counter is unchanged.  Synchronises the stream. */
+int ising_set_spins(ising_lattice* h, const uint8_t* host_spins);
+
+/* Number of sweeps done (the absolute index of the next sweep).  Together
+   with the spins this is the complete state: set_spins + set_sweep_count
+   restore a checkpoint exactly. */
+int ising_get_sweep_count(ising_lattice* h, uint64_t* t);
+int ising_set_sweep_count(ising_lattice* h, uint64_t t);
+
+/* Device pointer to the word lattice and its size in bytes (read-only view
+   for callers that move or inspect words themselves). */
+int ising_words(ising_lattice* h, void** dev_words, size_t* bytes);
+
+/* Kernel variant used by ising_sweep*: words_per_thread in {1, 2, 4} (same-
+   colour words of one row handled by one thread; 4 lets one Philox call serve
+   position 20 of four words) and block in {64, 128, 256, 512, 1024}.  Results
+   never depend on the choice. */
+int ising_set_plan(ising_lattice* h, int32_t words_per_thread, int32_t block);
+int ising_get_plan(ising_lattice* h, int32_t* words_per_thread, int32_t* block);
+
+/* Time every plan on this lattice's shape (on a scratch copy, the state is
+   not touched) and keep the fastest.  Synchronises.  best_ms (host, may be
+   NULL) receives the time per sweep of the chosen plan. */
+int ising_autotune(ising_lattice* h, double T, double* best_ms_per_sweep);
+
+/* Wait for all work enqueued on the handle's stream. */
+int ising_synchronize(ising_lattice* h);
+
+/* ------------------------------------------------------------------ */
+/* Batch: many independent lattices of mixed L and T advanced together  */
+/* ------------------------------------------------------------------ */
+
+/* n >= 1 lattices; L[i], seed[i], init[i] as for ising_create (host arrays).
+   All words live in one library-owned device arena. */
+int ising_batch_create(int32_t n, const int32_t* L, const uint64_t* seed, const int32_t* init, void* stream,
+                       ising_batch** out);
+int ising_batch_destroy(ising_batch* b);
+
+/* Advance every lattice i by n_sweeps at temperature T[i] (host array).
+   every = 0: no measurement.  every >= 1: after each every-th sweep of this
+   call, every lattice's E and M are added to its running sums (see
+   ising_batch_results) and, if dev_E / dev_M are non-NULL, stored at
+   dev_E[i * (n_sweeps/every) + k] (device pointers, int64).  The work is
+   enqueued as hipGraph replays of one chunk of sweeps. */
+int ising_batch_sweep(ising_batch* b, const double* T, int64_t n_sweeps, int32_t every, int64_t* dev_E,
+                      int64_t* dev_M);
+
+/* Per-lattice results into host arrays of n int64 (any may be NULL): the
+   current E and M, and sum_E, sum_absM, n_samples accumulated by every
+   measuring ising_batch_sweep since creation or the last reset.
+   Synchronises. */
+int ising_batch_results(ising_batch* b, int64_t* E, int64_t* M, int64_t* sum_E, int64_t* sum_absM,
+                        int64_t* n_samples);
+int ising_batch_reset_sums(ising_batch* b);
+
+/* Spins of lattice i (host array of L[i]^2 bytes); sweep counter of i. */
+int ising_batch_get_spins(ising_batch* b, int32_t i, uint8_t* host_spins);
+int ising_batch_get_sweep_count(ising_batch* b, int32_t i, uint64_t* t);
+
+/* Execution plan.  Lattices with L <= resident_max_L are advanced by one
+   workgroup each, all their sweeps of a chunk inside one launch, the lattice
+   held in LDS when it fits; the others by per-half-sweep launches over a
+   table of (lattice, row segment) work items with words_per_thread words per
+   thread.  sweeps_per_graph sweeps are captured in one hipGraph (rounded to
+   a multiple of `every`).  Results never depend on the plan. */
+typedef struct {
+    int32_t resident_max_L;   /* 0 = no resident lattices                    */
+    int32_t resident_block;   /* threads per resident workgroup (64..1024)   */
+    int32_t words_per_thread; /* 1, 2 or 4 (tiled path)                      */
+    int32_t tiled_block;      /* threads per tiled workgroup (64..1024)      */
+    int32_t sweeps_per_graph; /* >= 1                                        */
+} ising_batch_plan;
+
+int ising_batch_set_plan(ising_batch* b, const ising_batch_plan* plan);
+int ising_batch_get_plan(ising_batch* b, ising_batch_plan* plan);
+
+/* Autotuner: time candidate plans on a scratch batch of the same shapes
+   (this batch's state is untouched), keep the fastest, and record it in the
+   JSON file cache_path (may be NULL) keyed by GPU architecture and the
+   multiset of L.  If the file already holds an entry for that key, it is
+   used without timing.  Synchronises. */
+int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path, ising_batch_plan* chosen);
+
+/* ------------------------------------------------------------------ */
+/* Server: continuous batching of simulation requests                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t req_id;
+    int32_t L;
+    int32_t status;       /* ISING_OK, or a negative code if the request failed */
+    double T;
+    int64_t sweeps;
+    int64_t E, M;         /* observables of the final state                     */
+    double t_submit_s;    /* host clock (seconds, CLOCK_MONOTONIC) at submit    */
+    double t_admit_s;     /* when its lattice was created on the device         */
+    double t_done_s;      /* when its result was read back                      */
+} ising_result;
+
+/* A server holding at most max_slots resident lattices whose packed words
+   (ising_required_bytes) sum to at most hbm_budget bytes.  Work proceeds in
+   quanta of `quantum_sweeps` sweeps over all resident lattices; requests are
+   admitted in arrival order as slots and budget free up and leave as soon as
+   their sweeps are done. */
+int ising_server_create(size_t hbm_budget, int32_t max_slots, int32_t quantum_sweeps, void* stream,
+                        ising_server** out);
+
+/* Queue a request (host-side, never blocks on the GPU).  EINVAL for bad
+   arguments or a lattice larger than the whole budget. */
+int ising_server_submit(ising_server* s, uint64_t req_id, int32_t L, double T, int64_t sweeps, uint64_t seed,
+                        int32_t init);
+
+/* Run one scheduling quantum: retire finished lattices (reading E, M),
+   admit queued requests that fit, and launch one quantum of sweeps for all
+   resident lattices.  *active (may be NULL) receives the number of resident
+   lattices after the call.  Synchronises the previous quantum. */
+int ising_server_step(ising_server* s, int32_t* active);
+
+/* Move up to cap finished results into out (host array); *n receives how
+   many.  Returns ISING_OK even when *n == 0. */
+int ising_server_poll(ising_server* s, ising_result* out, int32_t cap, int32_t* n);
+
+/* Counts of queued, resident and finished-but-unpolled requests, and the
+   bytes of resident lattices. */
+int ising_server_stats(ising_server* s, int32_t* queued, int32_t* resident, int32_t* finished, size_t* bytes_in_use);
+
+int ising_server_destroy(ising_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISING_H */

@@ -1,0 +1,442 @@
+"""MI355X (gfx950) multi-spin-coded checkerboard Metropolis for the 2D Ising model.
+
+Thin Python binding of the C ABI in ``include/ising.h`` (``libising.so``, built
+in-tree by ``python -m paper_1811_04384_amd.build``).  Every step of the
+method runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch supplies device memory and the stream.  There is no CPU
+fallback: if the library is missing, importing the functions raises.
+
+Functions carry the C names (``ising_create``, ``ising_sweep``,
+``ising_observables``, ...); the classes ``Lattice``, ``Batch`` and ``Server``
+wrap handles for convenience.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (ISING_COLD, ISING_EAGAIN, ISING_EBUSY, ISING_EHIP, ISING_EINVAL, ISING_ENOMEM, ISING_HOT, ISING_OK,
+                   BatchPlan, Result)
+
+__all__ = [
+    "IsingError", "Lattice", "Batch", "Server", "BatchPlan", "Result", "load",
+    "ISING_OK", "ISING_EINVAL", "ISING_ENOMEM", "ISING_EHIP", "ISING_EBUSY", "ISING_EAGAIN", "ISING_COLD", "ISING_HOT",
+] + sorted(_lib.SIGNATURES)
+
+
+class IsingError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def load():
+    """The loaded ctypes library (raises ImportError if it is not built)."""
+    return _lib.load()
+
+
+def _check(rc):
+    if rc != ISING_OK:
+        raise IsingError(rc, _lib.load().ising_last_error().decode())
+    return rc
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(x):
+    """Device or host address of a torch tensor / numpy array / int / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return ctypes.c_void_p(x)
+    if hasattr(x, "data_ptr"):
+        return ctypes.c_void_p(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return ctypes.c_void_p(x.ctypes.data)
+    raise TypeError(f"cannot pass {type(x)} as a pointer")
+
+
+def _arr(a, ctype):
+    a = np.ascontiguousarray(a, dtype=np.dtype(ctype))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+# ---------------------------------------------------------------------------
+# Functions with the C names (argument marshalling only)
+# ---------------------------------------------------------------------------
+
+def ising_word_rows(L):
+    return int(_lib.load().ising_word_rows(int(L)))
+
+
+def ising_required_bytes(L):
+    return int(_lib.load().ising_required_bytes(int(L)))
+
+
+def ising_thresholds(T):
+    t4, t8 = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(_lib.load().ising_thresholds(float(T), ctypes.byref(t4), ctypes.byref(t8)))
+    return int(t4.value), int(t8.value)
+
+
+def ising_version():
+    return _lib.load().ising_version().decode()
+
+
+def ising_last_error():
+    return _lib.load().ising_last_error().decode()
+
+
+def ising_create(L, seed, init, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.load().ising_create(int(L), int(seed), int(init), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def ising_create_in(L, seed, init, dev_words, nbytes, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.load().ising_create_in(int(L), int(seed), int(init), _ptr(dev_words), int(nbytes), _stream(stream),
+                                       ctypes.byref(h)))
+    return h
+
+
+def ising_destroy(h):
+    _check(_lib.load().ising_destroy(h))
+
+
+def ising_sweep(h, T, n_sweeps):
+    _check(_lib.load().ising_sweep(h, float(T), int(n_sweeps)))
+
+
+def ising_sweep_measure(h, T, n_sweeps, every, dev_E, dev_M):
+    _check(_lib.load().ising_sweep_measure(h, float(T), int(n_sweeps), int(every), _ptr(dev_E), _ptr(dev_M)))
+
+
+def ising_observables(h):
+    E, M = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.load().ising_observables(h, ctypes.byref(E), ctypes.byref(M)))
+    return int(E.value), int(M.value)
+
+
+def ising_get_spins(h, L):
+    out = np.empty((L, L), dtype=np.uint8)
+    _check(_lib.load().ising_get_spins(h, _ptr(out)))
+    return out
+
+
+def ising_get_spins_region(h, r0, c0, nrows, ncols):
+    out = np.empty((nrows, ncols), dtype=np.uint8)
+    _check(_lib.load().ising_get_spins_region(h, int(r0), int(c0), int(nrows), int(ncols), _ptr(out)))
+    return out
+
+
+def ising_set_spins(h, spins):
+    s = np.ascontiguousarray(spins, dtype=np.uint8)
+    _check(_lib.load().ising_set_spins(h, _ptr(s)))
+
+
+def ising_get_sweep_count(h):
+    t = ctypes.c_uint64()
+    _check(_lib.load().ising_get_sweep_count(h, ctypes.byref(t)))
+    return int(t.value)
+
+
+def ising_set_sweep_count(h, t):
+    _check(_lib.load().ising_set_sweep_count(h, int(t)))
+
+
+def ising_words(h):
+    p, n = ctypes.c_void_p(), ctypes.c_size_t()
+    _check(_lib.load().ising_words(h, ctypes.byref(p), ctypes.byref(n)))
+    return int(p.value or 0), int(n.value)
+
+
+def ising_set_plan(h, words_per_thread, block):
+    _check(_lib.load().ising_set_plan(h, int(words_per_thread), int(block)))
+
+
+def ising_get_plan(h):
+    w, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.load().ising_get_plan(h, ctypes.byref(w), ctypes.byref(b)))
+    return int(w.value), int(b.value)
+
+
+def ising_autotune(h, T):
+    ms = ctypes.c_double()
+    _check(_lib.load().ising_autotune(h, float(T), ctypes.byref(ms)))
+    return float(ms.value)
+
+
+def ising_synchronize(h):
+    _check(_lib.load().ising_synchronize(h))
+
+
+def ising_batch_create(Ls, seeds, inits, stream=None):
+    Ls_, pL = _arr(Ls, ctypes.c_int32)
+    seeds_, pS = _arr(seeds, ctypes.c_uint64)
+    inits_, pI = _arr(inits, ctypes.c_int32)
+    h = ctypes.c_void_p()
+    _check(_lib.load().ising_batch_create(len(Ls_), pL, pS, pI, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def ising_batch_destroy(h):
+    _check(_lib.load().ising_batch_destroy(h))
+
+
+def ising_batch_sweep(h, T, n_sweeps, every=0, dev_E=None, dev_M=None):
+    T_, pT = _arr(T, ctypes.c_double)
+    _check(_lib.load().ising_batch_sweep(h, pT, int(n_sweeps), int(every), _ptr(dev_E), _ptr(dev_M)))
+
+
+def ising_batch_results(h, n):
+    outs = [np.zeros(n, dtype=np.int64) for _ in range(5)]
+    ptrs = [o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) for o in outs]
+    _check(_lib.load().ising_batch_results(h, *ptrs))
+    return dict(zip(("E", "M", "sum_E", "sum_absM", "n_samples"), outs))
+
+
+def ising_batch_reset_sums(h):
+    _check(_lib.load().ising_batch_reset_sums(h))
+
+
+def ising_batch_get_spins(h, i, L):
+    out = np.empty((L, L), dtype=np.uint8)
+    _check(_lib.load().ising_batch_get_spins(h, int(i), _ptr(out)))
+    return out
+
+
+def ising_batch_get_sweep_count(h, i):
+    t = ctypes.c_uint64()
+    _check(_lib.load().ising_batch_get_sweep_count(h, int(i), ctypes.byref(t)))
+    return int(t.value)
+
+
+def ising_batch_set_plan(h, plan):
+    p = plan if isinstance(plan, BatchPlan) else BatchPlan(**plan)
+    _check(_lib.load().ising_batch_set_plan(h, ctypes.byref(p)))
+
+
+def ising_batch_get_plan(h):
+    p = BatchPlan()
+    _check(_lib.load().ising_batch_get_plan(h, ctypes.byref(p)))
+    return p.as_dict()
+
+
+def ising_batch_autotune(h, T, cache_path=None):
+    T_, pT = _arr(T, ctypes.c_double)
+    p = BatchPlan()
+    _check(_lib.load().ising_batch_autotune(h, pT, cache_path.encode() if cache_path else None, ctypes.byref(p)))
+    return p.as_dict()
+
+
+def ising_server_create(hbm_budget, max_slots, quantum_sweeps, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.load().ising_server_create(int(hbm_budget), int(max_slots), int(quantum_sweeps), _stream(stream),
+                                           ctypes.byref(h)))
+    return h
+
+
+def ising_server_submit(h, req_id, L, T, sweeps, seed, init):
+    _check(_lib.load().ising_server_submit(h, int(req_id), int(L), float(T), int(sweeps), int(seed), int(init)))
+
+
+def ising_server_step(h):
+    a = ctypes.c_int32()
+    _check(_lib.load().ising_server_step(h, ctypes.byref(a)))
+    return int(a.value)
+
+
+def ising_server_poll(h, cap=4096):
+    buf = (Result * cap)()
+    n = ctypes.c_int32()
+    _check(_lib.load().ising_server_poll(h, buf, int(cap), ctypes.byref(n)))
+    out = []
+    for i in range(n.value):
+        r = buf[i]
+        out.append({k: getattr(r, k) for k, _ in Result._fields_})
+    return out
+
+
+def ising_server_stats(h):
+    q, r, f, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    _check(_lib.load().ising_server_stats(h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f), ctypes.byref(b)))
+    return {"queued": q.value, "resident": r.value, "finished": f.value, "bytes_in_use": b.value}
+
+
+def ising_server_destroy(h):
+    _check(_lib.load().ising_server_destroy(h))
+
+
+# ---------------------------------------------------------------------------
+# Convenience classes
+# ---------------------------------------------------------------------------
+
+class Lattice:
+    """One L x L lattice whose packed words live in a torch CUDA tensor."""
+
+    def __init__(self, L, seed, hot=True, stream=None, device="cuda"):
+        import torch
+
+        self.L = int(L)
+        self.seed = int(seed)
+        nbytes = ising_required_bytes(self.L)
+        if nbytes == 0:
+            raise IsingError(ISING_EINVAL, f"invalid lattice size L={L}")
+        self.stream = stream
+        self.words = torch.empty(nbytes // 8, dtype=torch.int64, device=device)
+        self.handle = ising_create_in(self.L, self.seed, ISING_HOT if hot else ISING_COLD, self.words, nbytes, stream)
+
+    def sweep(self, T, n):
+        ising_sweep(self.handle, T, n)
+        return self
+
+    def sweep_measure(self, T, n, every):
+        """Returns device int64 tensors (E, M) of n // every samples."""
+        import torch
+
+        k = int(n) // int(every)
+        E = torch.empty(max(k, 1), dtype=torch.int64, device=self.words.device)
+        M = torch.empty(max(k, 1), dtype=torch.int64, device=self.words.device)
+        ising_sweep_measure(self.handle, T, n, every, E, M)
+        return E[:k], M[:k]
+
+    def observables(self):
+        return ising_observables(self.handle)
+
+    def spins(self):
+        return ising_get_spins(self.handle, self.L)
+
+    def region(self, r0, c0, nrows, ncols):
+        return ising_get_spins_region(self.handle, r0, c0, nrows, ncols)
+
+    def set_spins(self, s):
+        ising_set_spins(self.handle, s)
+
+    @property
+    def t(self):
+        return ising_get_sweep_count(self.handle)
+
+    @t.setter
+    def t(self, value):
+        ising_set_sweep_count(self.handle, value)
+
+    def set_plan(self, words_per_thread, block):
+        ising_set_plan(self.handle, words_per_thread, block)
+
+    def plan(self):
+        return ising_get_plan(self.handle)
+
+    def autotune(self, T):
+        return ising_autotune(self.handle, T)
+
+    def synchronize(self):
+        ising_synchronize(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            ising_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many lattices of mixed L advanced together (one graph replay per chunk)."""
+
+    def __init__(self, Ls, seeds, hot=True, stream=None):
+        self.Ls = [int(x) for x in Ls]
+        hots = [hot] * len(self.Ls) if isinstance(hot, bool) else list(hot)
+        inits = [ISING_HOT if h else ISING_COLD for h in hots]
+        self.handle = ising_batch_create(self.Ls, seeds, inits, stream)
+
+    def __len__(self):
+        return len(self.Ls)
+
+    def sweep(self, T, n, every=0, series=False):
+        import torch
+
+        T = np.broadcast_to(np.asarray(T, dtype=np.float64), (len(self.Ls),))
+        if series and every > 0:
+            k = int(n) // int(every)
+            E = torch.empty(max(1, len(self.Ls) * k), dtype=torch.int64, device="cuda")
+            M = torch.empty_like(E)
+            ising_batch_sweep(self.handle, T, n, every, E, M)
+            return E[: len(self.Ls) * k].view(len(self.Ls), k), M[: len(self.Ls) * k].view(len(self.Ls), k)
+        ising_batch_sweep(self.handle, T, n, every)
+        return None
+
+    def results(self):
+        return ising_batch_results(self.handle, len(self.Ls))
+
+    def reset_sums(self):
+        ising_batch_reset_sums(self.handle)
+
+    def spins(self, i):
+        return ising_batch_get_spins(self.handle, i, self.Ls[i])
+
+    def sweep_count(self, i):
+        return ising_batch_get_sweep_count(self.handle, i)
+
+    def set_plan(self, **plan):
+        ising_batch_set_plan(self.handle, plan)
+
+    def plan(self):
+        return ising_batch_get_plan(self.handle)
+
+    def autotune(self, T, cache_path=None):
+        T = np.broadcast_to(np.asarray(T, dtype=np.float64), (len(self.Ls),))
+        return ising_batch_autotune(self.handle, T, cache_path)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            ising_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server."""
+
+    def __init__(self, hbm_budget, max_slots=4096, quantum_sweeps=100, stream=None):
+        self.handle = ising_server_create(hbm_budget, max_slots, quantum_sweeps, stream)
+
+    def submit(self, req_id, L, T, sweeps, seed=None, hot=True):
+        ising_server_submit(self.handle, req_id, L, T, sweeps, req_id if seed is None else seed,
+                            ISING_HOT if hot else ISING_COLD)
+
+    def step(self):
+        return ising_server_step(self.handle)
+
+    def poll(self, cap=4096):
+        return ising_server_poll(self.handle, cap)
+
+    def stats(self):
+        return ising_server_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            ising_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

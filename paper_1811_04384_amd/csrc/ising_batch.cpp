@@ -1,0 +1,613 @@
+// Batch engine: many independent lattices of mixed L and T advanced together.
+//
+// Two execution paths, chosen per lattice by the plan (results never depend
+// on it because every random number is a function of (seed, sweep, site)):
+//  - tiled: per half-sweep, one launch over a table of wavefronts covering
+//    every tiled lattice (each wavefront belongs to one lattice);
+//  - resident: one workgroup per lattice runs all sweeps of a chunk inside
+//    one launch, colours separated by workgroup barriers, the lattice kept in
+//    LDS when it fits.
+// A chunk of sweeps is captured once into a hipGraph (resident and tiled
+// work as parallel branches) and replayed; per-call parameters live in
+// device memory so replays need no re-capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ising_host.hpp"
+#include "ising_launch.hpp"
+
+using namespace ising;
+
+struct ising_batch {
+    int32_t n = 0;
+    std::vector<Geometry> geo;
+    std::vector<uint64_t> seed;
+    std::vector<size_t> offset;  // byte offset of each lattice in the arena
+    uint8_t* arena = nullptr;
+    size_t arena_bytes = 0;
+    hipStream_t stream = nullptr;  // caller's stream
+    hipStream_t cap = nullptr;     // private capture stream
+    hipStream_t side = nullptr;    // second branch of a captured chunk
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr, stage_ev = nullptr;
+    bool stage_pending = false;
+    int device = 0;
+    std::string arch;
+    LatticeDesc* d_desc = nullptr;
+    LatticeState* d_state = nullptr;
+    LatticeDesc* h_desc = nullptr;  // pinned staging of the descriptors
+    std::vector<uint64_t> t_host;
+    ising_batch_plan plan{};
+    // derived from the plan
+    std::vector<int32_t> resident;  // 0 tiled, 1 resident in LDS, 2 resident in global memory
+    std::vector<int64_t> units;
+    std::vector<int32_t> part_begin, part_count;
+    WaveItem* d_waves = nullptr;
+    int64_t n_waves = 0;
+    Partial* d_partials = nullptr;
+    int32_t* d_ids_lds = nullptr;
+    int32_t n_lds = 0;
+    size_t lds_bytes = 0;
+    int32_t* d_ids_glb = nullptr;
+    int32_t n_glb = 0;
+    int32_t n_tiled = 0;
+    std::map<std::pair<int32_t, int32_t>, hipGraphExec_t> graphs;  // (sweeps, every) -> executable
+};
+
+namespace {
+
+template <class T>
+void free_dev(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void drop_graphs(ising_batch* b) {
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+}
+
+void release(ising_batch* b) {
+    if (!b) return;
+    drop_graphs(b);
+    free_dev(b->arena);
+    free_dev(b->d_desc);
+    free_dev(b->d_state);
+    free_dev(b->d_waves);
+    free_dev(b->d_partials);
+    free_dev(b->d_ids_lds);
+    free_dev(b->d_ids_glb);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    if (b->join_ev) (void)hipEventDestroy(b->join_ev);
+    if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    delete b;
+}
+
+size_t lattice_bytes(const Geometry& g) { return (size_t)g.N * (size_t)g.L * sizeof(uint64_t); }
+
+int check_plan(const ising_batch_plan& p) {
+    if (p.resident_max_L < 0) return fail(ISING_EINVAL, "plan: resident_max_L must be >= 0");
+    if (!valid_block(p.resident_block, 1024)) return fail(ISING_EINVAL, "plan: resident_block must be a multiple of 64 in [64, 1024]");
+    if (p.words_per_thread != 1 && p.words_per_thread != 2 && p.words_per_thread != 4)
+        return fail(ISING_EINVAL, "plan: words_per_thread must be 1, 2 or 4");
+    if (!valid_block(p.tiled_block, 256)) return fail(ISING_EINVAL, "plan: tiled_block must be a multiple of 64 in [64, 256]");
+    if (p.sweeps_per_graph < 1 || p.sweeps_per_graph > 100000) return fail(ISING_EINVAL, "plan: sweeps_per_graph must be in [1, 100000]");
+    return ISING_OK;
+}
+
+// Upload the descriptors (pinned staging; the previous upload must have
+// completed before the staging buffer is rewritten).
+int upload_descs(ising_batch* b, const double* T, int64_t* dev_E, int64_t* dev_M, int64_t samples_per_lattice) {
+    if (b->stage_pending) {
+        ISING_HIP(hipEventSynchronize(b->stage_ev));
+        b->stage_pending = false;
+    }
+    for (int32_t i = 0; i < b->n; ++i) {
+        LatticeDesc& d = b->h_desc[i];
+        const Geometry& g = b->geo[i];
+        d.W = reinterpret_cast<uint64_t*>(b->arena + b->offset[i]);
+        d.L = g.L;
+        d.N = g.N;
+        d.istar = g.istar;
+        d.sh_star = g.sh_star;
+        d.k0 = (uint32_t)b->seed[i];
+        d.k1 = (uint32_t)(b->seed[i] >> 32);
+        if (T) thresholds_of(T[i], &d.t4, &d.t8);
+        else d.t4 = d.t8 = 0;
+        d.units = b->units.empty() ? 0 : b->units[i];
+        d.segs = segments_per_row(g.L, b->plan.words_per_thread);
+        d.resident = b->resident.empty() ? 0 : (b->resident[i] != 0);
+        d.part_begin = b->part_begin.empty() ? 0 : b->part_begin[i];
+        d.part_count = b->part_count.empty() ? 0 : b->part_count[i];
+        d.sweep_limit = 0x7FFFFFFF;
+        d.pad_ = 0;
+        d.series_E = dev_E ? dev_E + (int64_t)i * samples_per_lattice : nullptr;
+        d.series_M = dev_M ? dev_M + (int64_t)i * samples_per_lattice : nullptr;
+    }
+    ISING_HIP(hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(LatticeDesc) * b->n, hipMemcpyHostToDevice, b->stream));
+    ISING_HIP(hipEventRecord(b->stage_ev, b->stream));
+    b->stage_pending = true;
+    return ISING_OK;
+}
+
+int apply_plan(ising_batch* b, const ising_batch_plan& p) {
+    int rc = check_plan(p);
+    if (rc != ISING_OK) return rc;
+    ISING_HIP(hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    free_dev(b->d_waves);
+    free_dev(b->d_partials);
+    free_dev(b->d_ids_lds);
+    free_dev(b->d_ids_glb);
+    b->plan = p;
+    const size_t lds_limit = resident_lds_limit(b->device);
+    b->resident.assign(b->n, 0);
+    b->units.assign(b->n, 0);
+    b->part_begin.assign(b->n, 0);
+    b->part_count.assign(b->n, 0);
+    std::vector<int32_t> ids_lds, ids_glb;
+    std::vector<WaveItem> waves;
+    size_t max_lds = 0;
+    for (int32_t i = 0; i < b->n; ++i) {
+        const Geometry& g = b->geo[i];
+        if (g.L <= p.resident_max_L) {
+            if (lattice_bytes(g) <= lds_limit) {
+                b->resident[i] = 1;
+                ids_lds.push_back(i);
+                max_lds = std::max(max_lds, lattice_bytes(g));
+            } else {
+                b->resident[i] = 2;
+                ids_glb.push_back(i);
+            }
+            continue;
+        }
+        const int64_t u = units_per_colour(g, p.words_per_thread);
+        b->units[i] = u;
+        b->part_begin[i] = (int32_t)waves.size();
+        for (int64_t u0 = 0; u0 < u; u0 += 64) waves.push_back({i, (int32_t)u0});
+        b->part_count[i] = (int32_t)waves.size() - b->part_begin[i];
+    }
+    b->n_waves = (int64_t)waves.size();
+    b->n_lds = (int32_t)ids_lds.size();
+    b->n_glb = (int32_t)ids_glb.size();
+    b->n_tiled = b->n - b->n_lds - b->n_glb;
+    b->lds_bytes = max_lds;
+    if (!waves.empty()) {
+        ISING_HIP(hipMalloc(&b->d_waves, sizeof(WaveItem) * waves.size()));
+        ISING_HIP(hipMemcpy(b->d_waves, waves.data(), sizeof(WaveItem) * waves.size(), hipMemcpyHostToDevice));
+        ISING_HIP(hipMalloc(&b->d_partials, sizeof(Partial) * waves.size()));
+    }
+    if (!ids_lds.empty()) {
+        ISING_HIP(hipMalloc(&b->d_ids_lds, sizeof(int32_t) * ids_lds.size()));
+        ISING_HIP(hipMemcpy(b->d_ids_lds, ids_lds.data(), sizeof(int32_t) * ids_lds.size(), hipMemcpyHostToDevice));
+        ISING_HIP(set_resident_lds(p.words_per_thread, max_lds));
+    }
+    if (!ids_glb.empty()) {
+        ISING_HIP(hipMalloc(&b->d_ids_glb, sizeof(int32_t) * ids_glb.size()));
+        ISING_HIP(hipMemcpy(b->d_ids_glb, ids_glb.data(), sizeof(int32_t) * ids_glb.size(), hipMemcpyHostToDevice));
+    }
+    return upload_descs(b, nullptr, nullptr, nullptr, 0);
+}
+
+// Enqueue one chunk of k sweeps (sample after local sweeps s with
+// (s + 1) % every == 0) on stream s0, resident work on stream s1.
+int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipStream_t s1) {
+    const ising_batch_plan& p = b->plan;
+    const bool fork = (b->n_lds + b->n_glb) > 0 && b->n_tiled > 0 && s1 != nullptr;
+    hipStream_t rs = fork ? s1 : s0;
+    if (fork) {
+        ISING_HIP(hipEventRecord(b->fork_ev, s0));
+        ISING_HIP(hipStreamWaitEvent(s1, b->fork_ev, 0));
+    }
+    if (b->n_lds)
+        ISING_HIP(launch_resident(p.words_per_thread, p.resident_block, b->d_desc, b->d_state, b->d_ids_lds, b->n_lds,
+                                  k, every, b->lds_bytes, rs));
+    if (b->n_glb)
+        ISING_HIP(launch_resident(p.words_per_thread, p.resident_block, b->d_desc, b->d_state, b->d_ids_glb, b->n_glb,
+                                  k, every, 0, rs));
+    if (b->n_tiled) {
+        for (int32_t s = 0; s < k; ++s) {
+            const bool meas = every > 0 && (s + 1) % every == 0;
+            ISING_HIP(launch_halfsweep_multi(p.words_per_thread, p.tiled_block, b->d_desc, b->d_state, b->d_waves,
+                                             b->n_waves, 0, (uint32_t)s, nullptr, s0));
+            ISING_HIP(launch_halfsweep_multi(p.words_per_thread, p.tiled_block, b->d_desc, b->d_state, b->d_waves,
+                                             b->n_waves, 1, (uint32_t)s, meas ? b->d_partials : nullptr, s0));
+            if (meas) ISING_HIP(launch_finalize_multi(b->d_desc, b->d_state, b->n, b->d_partials, (uint32_t)s, s0));
+        }
+    }
+    if (fork) {
+        ISING_HIP(hipEventRecord(b->join_ev, s1));
+        ISING_HIP(hipStreamWaitEvent(s0, b->join_ev, 0));
+    }
+    ISING_HIP(launch_advance(b->d_desc, b->d_state, b->n, (uint32_t)k, s0));
+    return ISING_OK;
+}
+
+int get_graph(ising_batch* b, int32_t k, int32_t every, hipGraphExec_t* out) {
+    auto it = b->graphs.find({k, every});
+    if (it != b->graphs.end()) {
+        *out = it->second;
+        return ISING_OK;
+    }
+    ISING_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_chunk(b, k, every, b->cap, b->side);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap, &graph);
+    if (rc != ISING_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    b->graphs[{k, every}] = exec;
+    *out = exec;
+    return ISING_OK;
+}
+
+int32_t chunk_sweeps(const ising_batch* b, int32_t every) {
+    int32_t K = b->plan.sweeps_per_graph;
+    if (every > 0) K = std::max(every, (K / every) * every);
+    return K;
+}
+
+int sweep_impl(ising_batch* b, const double* T, int64_t n, int32_t every, int64_t* dev_E, int64_t* dev_M) {
+    if (!b || !T) return fail(ISING_EINVAL, "ising_batch_sweep: null argument");
+    if (n < 0) return fail(ISING_EINVAL, "ising_batch_sweep: n_sweeps must be >= 0");
+    if (every < 0) return fail(ISING_EINVAL, "ising_batch_sweep: every must be >= 0");
+    if ((dev_E || dev_M) && every == 0) return fail(ISING_EINVAL, "ising_batch_sweep: series need every >= 1");
+    for (int32_t i = 0; i < b->n; ++i)
+        if (!valid_T(T[i])) return fail(ISING_EINVAL, "ising_batch_sweep: T[%d] must be finite and > 0", i);
+    const int64_t samples = every > 0 ? n / every : 0;
+    int rc = upload_descs(b, T, dev_E, dev_M, samples);
+    if (rc != ISING_OK) return rc;
+    ISING_HIP(launch_begin_call(b->d_state, b->n, b->stream));
+    const int32_t K = chunk_sweeps(b, every);
+    for (int64_t done = 0; done < n;) {
+        const int32_t k = (int32_t)std::min<int64_t>(K, n - done);
+        hipGraphExec_t g = nullptr;
+        rc = get_graph(b, k, every, &g);
+        if (rc != ISING_OK) return rc;
+        ISING_HIP(hipGraphLaunch(g, b->stream));
+        done += k;
+    }
+    for (auto& t : b->t_host) t += (uint64_t)n;
+    return ISING_OK;
+}
+
+int create_impl(int32_t n, const int32_t* L, const uint64_t* seed, const int32_t* init, void* stream,
+                ising_batch** out, const ising_batch_plan* plan) {
+    if (!out) return fail(ISING_EINVAL, "ising_batch_create: null output");
+    *out = nullptr;
+    if (n < 1 || !L || !seed || !init) return fail(ISING_EINVAL, "ising_batch_create: need n >= 1 and non-null arrays");
+    for (int32_t i = 0; i < n; ++i) {
+        if (!valid_L(L[i])) return fail(ISING_EINVAL, "ising_batch_create: L[%d] = %d invalid (even, 4..%d)", i, L[i], kMaxL);
+        if (init[i] != ISING_COLD && init[i] != ISING_HOT) return fail(ISING_EINVAL, "ising_batch_create: init[%d] must be 0 or 1", i);
+    }
+    ising_batch* b = new (std::nothrow) ising_batch();
+    if (!b) return fail(ISING_ENOMEM, "ising_batch_create: host allocation failed");
+    b->n = n;
+    b->stream = (hipStream_t)stream;
+    b->geo.resize(n);
+    b->seed.assign(seed, seed + n);
+    b->offset.resize(n);
+    b->t_host.assign(n, 0);
+    size_t off = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        b->geo[i] = make_geometry(L[i]);
+        b->offset[i] = off;
+        off += (lattice_bytes(b->geo[i]) + 255) & ~(size_t)255;
+    }
+    b->arena_bytes = off;
+    hipError_t e = hipGetDevice(&b->device);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, b->device);
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "ising_batch_create: device query");
+    }
+    b->arch = prop.gcnArchName;
+    b->arch = b->arch.substr(0, b->arch.find(':'));
+    e = hipMalloc(&b->arena, b->arena_bytes);
+    if (e != hipSuccess) {
+        b->arena = nullptr;
+        release(b);
+        return fail(ISING_ENOMEM, "ising_batch_create: hipMalloc of %zu bytes failed", off);
+    }
+    if (e == hipSuccess) e = hipMalloc(&b->d_desc, sizeof(LatticeDesc) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_state, sizeof(LatticeState) * n);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_desc, sizeof(LatticeDesc) * n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->stage_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_state, 0, sizeof(LatticeState) * n, b->stream);
+    for (int32_t i = 0; i < n && e == hipSuccess; ++i)
+        e = launch_init(reinterpret_cast<uint64_t*>(b->arena + b->offset[i]), b->geo[i], seed[i], init[i], b->stream);
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "ising_batch_create");
+    }
+    ising_batch_plan p;
+    if (plan) {
+        p = *plan;
+    } else {
+        // default: lattices that fit in one workgroup's LDS are resident
+        const size_t lim = resident_lds_limit(b->device);
+        p.resident_max_L = 0;
+        for (int32_t i = 0; i < n; ++i)
+            if (lattice_bytes(b->geo[i]) <= lim && b->geo[i].L <= 256) p.resident_max_L = std::max(p.resident_max_L, b->geo[i].L);
+        p.resident_block = 256;
+        p.words_per_thread = 4;
+        p.tiled_block = 256;
+        p.sweeps_per_graph = 50;
+    }
+    int rc = apply_plan(b, p);
+    if (rc != ISING_OK) {
+        release(b);
+        return rc;
+    }
+    *out = b;
+    return ISING_OK;
+}
+
+std::string cache_key(const ising_batch* b) {
+    std::map<int32_t, int32_t> hist;
+    for (const auto& g : b->geo) hist[g.L] += 1;
+    std::ostringstream os;
+    os << b->arch << "|";
+    bool first = true;
+    for (auto& kv : hist) {
+        os << (first ? "" : ",") << kv.first << "x" << kv.second;
+        first = false;
+    }
+    return os.str();
+}
+
+bool cache_lookup(const char* path, const std::string& key, ising_batch_plan* p) {
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    const std::string want = "\"" + key + "\":";
+    while (std::getline(f, line)) {
+        const size_t at = line.find(want);
+        if (at == std::string::npos) continue;
+        ising_batch_plan q;
+        if (std::sscanf(line.c_str() + at + want.size(),
+                        " {\"resident_max_L\": %d, \"resident_block\": %d, \"words_per_thread\": %d, \"tiled_block\": %d, "
+                        "\"sweeps_per_graph\": %d",
+                        &q.resident_max_L, &q.resident_block, &q.words_per_thread, &q.tiled_block,
+                        &q.sweeps_per_graph) == 5) {
+            *p = q;
+            return true;
+        }
+    }
+    return false;
+}
+
+void cache_store(const char* path, const std::string& key, const ising_batch_plan& p, double ms) {
+    if (!path) return;
+    std::vector<std::string> lines;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line)) {
+            if (line.find("\"" + key + "\":") != std::string::npos) continue;
+            if (line.find("\":") == std::string::npos) continue;  // braces
+            while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+            lines.push_back(line);
+        }
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof buf,
+                  "\"%s\": {\"resident_max_L\": %d, \"resident_block\": %d, \"words_per_thread\": %d, \"tiled_block\": "
+                  "%d, \"sweeps_per_graph\": %d, \"ms_per_sweep\": %.6f}",
+                  key.c_str(), p.resident_max_L, p.resident_block, p.words_per_thread, p.tiled_block, p.sweeps_per_graph,
+                  ms);
+    lines.push_back(buf);
+    std::ofstream f(path, std::ios::trunc);
+    f << "{\n";
+    for (size_t i = 0; i < lines.size(); ++i) f << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+    f << "}\n";
+}
+
+// Time `sweeps` sweeps of a scratch batch under plan p; ms per sweep.
+int time_plan(ising_batch* s, const ising_batch_plan& p, const double* T, int32_t sweeps, double* ms_per_sweep) {
+    int rc = apply_plan(s, p);
+    if (rc != ISING_OK) return rc;
+    rc = sweep_impl(s, T, std::min(sweeps, p.sweeps_per_graph), 0, nullptr, nullptr);  // capture + warm-up
+    if (rc != ISING_OK) return rc;
+    hipEvent_t e0, e1;
+    ISING_HIP(hipEventCreate(&e0));
+    ISING_HIP(hipEventCreate(&e1));
+    hipError_t e = hipEventRecord(e0, s->stream);
+    if (e == hipSuccess) rc = sweep_impl(s, T, sweeps, 0, nullptr, nullptr);
+    if (e == hipSuccess && rc == ISING_OK) e = hipEventRecord(e1, s->stream);
+    if (e == hipSuccess && rc == ISING_OK) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess && rc == ISING_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != ISING_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    *ms_per_sweep = ms / sweeps;
+    return ISING_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ising_batch_create(int32_t n, const int32_t* L, const uint64_t* seed, const int32_t* init, void* stream,
+                       ising_batch** out) {
+    return create_impl(n, L, seed, init, stream, out, nullptr);
+}
+
+int ising_batch_destroy(ising_batch* b) {
+    if (!b) return ISING_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    release(b);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return ISING_OK;
+}
+
+int ising_batch_sweep(ising_batch* b, const double* T, int64_t n_sweeps, int32_t every, int64_t* dev_E,
+                      int64_t* dev_M) {
+    return sweep_impl(b, T, n_sweeps, every, dev_E, dev_M);
+}
+
+int ising_batch_results(ising_batch* b, int64_t* E, int64_t* M, int64_t* sum_E, int64_t* sum_absM,
+                        int64_t* n_samples) {
+    if (!b) return fail(ISING_EINVAL, "ising_batch_results: null handle");
+    if (E || M) ISING_HIP(launch_observe_multi(b->d_desc, b->d_state, nullptr, b->n, b->stream));
+    std::vector<LatticeState> st(b->n);
+    ISING_HIP(hipMemcpyAsync(st.data(), b->d_state, sizeof(LatticeState) * b->n, hipMemcpyDeviceToHost, b->stream));
+    ISING_HIP(hipStreamSynchronize(b->stream));
+    for (int32_t i = 0; i < b->n; ++i) {
+        if (E) E[i] = st[i].last_E;
+        if (M) M[i] = st[i].last_M;
+        if (sum_E) sum_E[i] = st[i].sum_E;
+        if (sum_absM) sum_absM[i] = st[i].sum_absM;
+        if (n_samples) n_samples[i] = st[i].n_samples;
+    }
+    return ISING_OK;
+}
+
+int ising_batch_reset_sums(ising_batch* b) {
+    if (!b) return fail(ISING_EINVAL, "ising_batch_reset_sums: null handle");
+    ISING_HIP(launch_reset_sums(b->d_state, b->n, b->stream));
+    return ISING_OK;
+}
+
+int ising_batch_get_spins(ising_batch* b, int32_t i, uint8_t* host) {
+    if (!b || !host) return fail(ISING_EINVAL, "ising_batch_get_spins: null argument");
+    if (i < 0 || i >= b->n) return fail(ISING_EINVAL, "ising_batch_get_spins: index %d out of range", i);
+    const Geometry& g = b->geo[i];
+    const size_t bytes = (size_t)g.L * (size_t)g.L;
+    uint8_t* d = nullptr;
+    ISING_HIP(hipMalloc(&d, bytes));
+    hipError_t e = launch_unpack(reinterpret_cast<const uint64_t*>(b->arena + b->offset[i]), g, 0, 0, g.L, g.L, d, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipError_t e2 = hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "ising_batch_get_spins");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
+    return ISING_OK;
+}
+
+int ising_batch_get_sweep_count(ising_batch* b, int32_t i, uint64_t* t) {
+    if (!b || !t) return fail(ISING_EINVAL, "ising_batch_get_sweep_count: null argument");
+    if (i < 0 || i >= b->n) return fail(ISING_EINVAL, "ising_batch_get_sweep_count: index %d out of range", i);
+    *t = b->t_host[i];
+    return ISING_OK;
+}
+
+int ising_batch_set_plan(ising_batch* b, const ising_batch_plan* plan) {
+    if (!b || !plan) return fail(ISING_EINVAL, "ising_batch_set_plan: null argument");
+    return apply_plan(b, *plan);
+}
+
+int ising_batch_get_plan(ising_batch* b, ising_batch_plan* plan) {
+    if (!b || !plan) return fail(ISING_EINVAL, "ising_batch_get_plan: null argument");
+    *plan = b->plan;
+    return ISING_OK;
+}
+
+int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path, ising_batch_plan* chosen) {
+    if (!b || !T) return fail(ISING_EINVAL, "ising_batch_autotune: null argument");
+    for (int32_t i = 0; i < b->n; ++i)
+        if (!valid_T(T[i])) return fail(ISING_EINVAL, "ising_batch_autotune: T[%d] must be finite and > 0", i);
+    const std::string key = cache_key(b);
+    ising_batch_plan best;
+    if (cache_lookup(cache_path, key, &best)) {
+        int rc = apply_plan(b, best);
+        if (rc == ISING_OK && chosen) *chosen = best;
+        return rc;
+    }
+    // scratch batch of the same shapes (hot start, seeds = index)
+    std::vector<int32_t> L(b->n), init(b->n, ISING_HOT);
+    std::vector<uint64_t> seeds(b->n);
+    double total_spins = 0;
+    std::vector<int32_t> distinct;
+    for (int32_t i = 0; i < b->n; ++i) {
+        L[i] = b->geo[i].L;
+        seeds[i] = (uint64_t)i;
+        total_spins += (double)L[i] * L[i];
+        distinct.push_back(L[i]);
+    }
+    std::sort(distinct.begin(), distinct.end());
+    distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+    ISING_HIP(hipStreamSynchronize(b->stream));
+    ising_batch* s = nullptr;
+    ising_batch_plan p0 = b->plan;
+    int rc = create_impl(b->n, L.data(), seeds.data(), init.data(), b->stream, &s, &p0);
+    if (rc != ISING_OK) return rc;
+    // about 20 ms of work per timing at ~1 attempt/ps
+    const int32_t sweeps = (int32_t)std::max(4.0, std::min(2000.0, 2e10 / std::max(total_spins, 1.0)));
+    double best_ms = 1e300;
+    best = p0;
+    auto consider = [&](const ising_batch_plan& p) -> int {
+        double ms = 0;
+        int r = time_plan(s, p, T, sweeps, &ms);
+        if (r != ISING_OK) return r;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = p;
+        }
+        return ISING_OK;
+    };
+    // 1) tiled shape with everything tiled
+    for (int wpt : {1, 2, 4})
+        for (int blk : {128, 256}) {
+            if (rc != ISING_OK) break;
+            ising_batch_plan p = best;
+            p.resident_max_L = 0;
+            p.words_per_thread = wpt;
+            p.tiled_block = blk;
+            p.sweeps_per_graph = std::min(sweeps, 50);
+            rc = consider(p);
+        }
+    // 2) which sizes go resident, and the resident workgroup size
+    const ising_batch_plan tiled_best = best;
+    for (int32_t Lr : distinct)
+        for (int rb : {256, 512, 1024}) {
+            if (rc != ISING_OK) break;
+            ising_batch_plan p = tiled_best;
+            p.resident_max_L = Lr;
+            p.resident_block = rb;
+            rc = consider(p);
+        }
+    // 3) sweeps per graph
+    const ising_batch_plan shape_best = best;
+    for (int k : {10, 25, 100, 250}) {
+        if (rc != ISING_OK) break;
+        ising_batch_plan p = shape_best;
+        p.sweeps_per_graph = std::min(k, sweeps);
+        rc = consider(p);
+    }
+    ising_batch_destroy(s);
+    if (rc != ISING_OK) return rc;
+    rc = apply_plan(b, best);
+    if (rc != ISING_OK) return rc;
+    cache_store(cache_path, key, best, best_ms);
+    if (chosen) *chosen = best;
+    return ISING_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Types shared by the host library and its kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace ising {
+
+// Largest supported linear size; keeps the Philox counter word I*L + J
+// below 2^32 (N(L) * L < 2^32 for L <= 2^18).
+constexpr int32_t kMaxL = 1 << 18;
+
+// Geometry of one lattice (Section 3 layout with the even-N reading).
+struct Geometry {
+    int32_t L;        // linear size (even)
+    int32_t N;        // word rows: smallest even N with 21 N >= L
+    int32_t istar;    // word row holding lattice row L-1: (L-1) mod N
+    int32_t sh_star;  // its bit: 3 * (20 - (L-1) div N)
+};
+
+inline Geometry make_geometry(int32_t L) {
+    Geometry g;
+    g.L = L;
+    int32_t n = (L + 20) / 21;
+    if (n & 1) n += 1;
+    g.N = n;
+    g.istar = (L - 1) % n;
+    g.sh_star = 3 * (20 - (L - 1) / n);
+    return g;
+}
+
+// Everything a half-sweep of one lattice needs; wave-uniform.
+struct SweepArgs {
+    int32_t L, N, istar, sh_star;
+    uint32_t t_lo, t_hi;  // absolute sweep index
+    uint32_t k0, k1;      // Philox key = seed
+    uint32_t t4, t8;      // acceptance thresholds
+};
+
+// Per-lattice parameters of a batch, written by the host before each call
+// and read-only for every kernel.
+struct LatticeDesc {
+    uint64_t* W;              // word lattice, N x L
+    int32_t L, N, istar, sh_star;
+    uint32_t k0, k1;          // seed
+    uint32_t t4, t8;          // thresholds of the current call
+    int64_t units;            // tiled work units (row segments) of one colour
+    int32_t segs;             // segments per row for the current tiled plan
+    int32_t resident;         // 1: advanced by the resident kernel
+    int32_t part_begin;       // first partial-sum slot of this lattice
+    int32_t part_count;       // number of partial-sum slots
+    int32_t sweep_limit;      // sweeps of the current chunk this lattice takes part in
+    int32_t pad_;
+    int64_t* series_E;        // per-call sample outputs (may be null)
+    int64_t* series_M;
+};
+
+// Per-lattice state of a batch, written only by kernels (the host reads it
+// back and zeroes it at creation).
+struct LatticeState {
+    uint64_t t;               // absolute index of the next sweep
+    int64_t series_idx;       // next sample slot of the current call
+    int64_t n_samples;        // accumulated samples
+    int64_t sum_E;            // sum of E over samples
+    int64_t sum_absM;         // sum of |M| over samples
+    int64_t last_E, last_M;   // most recent sample or observation
+};
+
+// One wavefront of a tiled half-sweep launch: 64 consecutive work units of
+// one lattice.
+struct WaveItem {
+    int32_t lattice;
+    int32_t unit0;  // first unit handled by lane 0 (units beyond `units` idle)
+};
+
+// Partial sums of one wavefront: antiparallel bonds and up spins.
+struct Partial {
+    uint32_t anti;
+    uint32_t ups;
+};
+
+}  // namespace ising

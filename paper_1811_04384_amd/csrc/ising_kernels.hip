@@ -1,0 +1,548 @@
+// gfx950 kernels of the multi-spin-coded checkerboard Metropolis sweep and
+// their launchers.  See ising_device.hpp for the word layout and the
+// per-word update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ising_device.hpp"
+#include "ising_launch.hpp"
+
+namespace ising {
+
+namespace {
+
+constexpr int kTiledMaxBlock = 256;
+constexpr int kResidentMaxBlock = 1024;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// ---------------------------------------------------------------------------
+// Initial state.  One thread per word.  Hot start: a site is up iff its
+// stream-0 draw at t = 0 is below 2^31 (the random initialisation of
+// Section 5.1 with a reproducible generator).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_init(uint64_t* __restrict__ W, Geometry g, uint32_t k0, uint32_t k1,
+                                              int hot) {
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n_words = (uint32_t)g.N * (uint32_t)g.L;
+    if (idx >= n_words) return;
+    const int I = (int)(idx / (uint32_t)g.L);
+    const int J = (int)(idx - (uint32_t)I * (uint32_t)g.L);
+    const uint64_t live = live_mask(I, g.L, g.N);
+    if (!hot) {
+        W[idx] = live;
+        return;
+    }
+    const uint32_t row_base = (uint32_t)I * (uint32_t)g.L;
+    uint64_t v = 0;
+#pragma unroll
+    for (int blk = 0; blk < 5; ++blk) {
+        const U4 r = philox_lane_c1(0u, row_base + (uint32_t)J, 0u, (uint32_t)blk, k0, k1);
+        const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = 4 * blk + j;
+            v |= (uint64_t)(u[j] >> 31 ^ 1u) << (3 * (20 - p));
+        }
+    }
+    {
+        const uint32_t col = ((uint32_t)J & ~7u) | ((uint32_t)J & 1u);
+        const U4 r = philox_lane_c1(0u, row_base + col, 0u, 5u, k0, k1);
+        const uint32_t q = ((uint32_t)J >> 1) & 3u;
+        const uint32_t u = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
+        v |= (uint64_t)(u >> 31 ^ 1u);
+    }
+    W[idx] = v & live;
+}
+
+// ---------------------------------------------------------------------------
+// Half-sweep of one lattice held in global memory.  One thread per row
+// segment; a segment holds WPT words of the colour being updated.
+// ---------------------------------------------------------------------------
+template <int WPT, bool MEASURE>
+__global__ void __launch_bounds__(kTiledMaxBlock)
+    k_halfsweep_single(uint64_t* __restrict__ W, SweepArgs a, int32_t segs, uint32_t units, int colour,
+                       Partial* __restrict__ partials) {
+    const uint32_t unit = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t anti = 0, ups = 0;
+    if (unit < units) {
+        const int I = (int)(unit / (uint32_t)segs);
+        const int seg = (int)(unit - (uint32_t)I * (uint32_t)segs);
+        const int J0 = seg * 2 * WPT + ((I + colour) & 1);
+        const size_t L = (size_t)a.L;
+        auto ld = [&](int i, int j) { return W[(size_t)i * L + j]; };
+        auto st = [&](int i, int j, uint64_t v) { W[(size_t)i * L + j] = v; };
+        update_segment<WPT, MEASURE>(ld, st, I, J0, a, anti, ups);
+    }
+    if (MEASURE) {
+        anti = wave_sum_u32(anti);
+        ups = wave_sum_u32(ups);
+        if (lane_id() == 0) partials[unit >> 6] = {anti, ups};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Half-sweep over a table of wavefronts covering many lattices.  Every
+// wavefront belongs to one lattice, so the lattice's parameters (key, sweep
+// index, thresholds) are wave-uniform and live in scalar registers.
+// ---------------------------------------------------------------------------
+template <int WPT, bool MEASURE>
+__global__ void __launch_bounds__(kTiledMaxBlock)
+    k_halfsweep_multi(const LatticeDesc* __restrict__ descs, const LatticeState* __restrict__ states,
+                      const WaveItem* __restrict__ waves, uint32_t n_waves, int colour, uint32_t sweep_off,
+                      Partial* __restrict__ partials) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (wave >= n_waves) return;
+    const WaveItem item = waves[wave];
+    const LatticeDesc& d = descs[item.lattice];
+    if (sweep_off >= (uint32_t)d.sweep_limit) {  // this lattice has finished its sweeps of the chunk
+        if (MEASURE && lane_id() == 0) partials[wave] = {0u, 0u};
+        return;
+    }
+    const uint64_t t = states[item.lattice].t + sweep_off;
+    const SweepArgs a = {d.L, d.N, d.istar, d.sh_star, (uint32_t)t, (uint32_t)(t >> 32), d.k0, d.k1, d.t4, d.t8};
+    uint64_t* __restrict__ W = d.W;
+    const uint32_t unit = (uint32_t)item.unit0 + (uint32_t)lane_id();
+    uint32_t anti = 0, ups = 0;
+    if (unit < (uint32_t)d.units) {
+        const int segs = d.segs;
+        const int I = (int)(unit / (uint32_t)segs);
+        const int seg = (int)(unit - (uint32_t)I * (uint32_t)segs);
+        const int J0 = seg * 2 * WPT + ((I + colour) & 1);
+        const size_t L = (size_t)a.L;
+        auto ld = [&](int i, int j) { return W[(size_t)i * L + j]; };
+        auto st = [&](int i, int j, uint64_t v) { W[(size_t)i * L + j] = v; };
+        update_segment<WPT, MEASURE>(ld, st, I, J0, a, anti, ups);
+    }
+    if (MEASURE) {
+        anti = wave_sum_u32(anti);
+        ups = wave_sum_u32(ups);
+        if (lane_id() == 0) partials[wave] = {anti, ups};
+    }
+}
+
+__device__ __forceinline__ void block_sum2(uint64_t& x, uint64_t& y, uint64_t* red /* 2 * 16 */) {
+    x = wave_sum_u64(x);
+    y = wave_sum_u64(y);
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        red[wv] = x;
+        red[16 + wv] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        uint64_t sx = 0, sy = 0;
+        for (int i = 0; i < nw; ++i) {
+            sx += red[i];
+            sy += red[16 + i];
+        }
+        x = sx;
+        y = sy;
+    }
+    __syncthreads();
+}
+
+// E = 2 A - 2 L^2 (A antiparallel bonds out of 2 L^2), M = 2 U - L^2.
+__device__ __forceinline__ void energy_magnetisation(uint64_t anti, uint64_t ups, int32_t L, int64_t& E, int64_t& M) {
+    const int64_t n = (int64_t)L * (int64_t)L;
+    E = 2 * (int64_t)anti - 2 * n;
+    M = 2 * (int64_t)ups - n;
+}
+
+__global__ void __launch_bounds__(1024) k_finalize_single(const Partial* __restrict__ partials, int64_t n_partials,
+                                                          int32_t L, int64_t* series_E, int64_t* series_M,
+                                                          int64_t idx, int64_t* out_EM) {
+    __shared__ uint64_t red[32];
+    uint64_t anti = 0, ups = 0;
+    for (int64_t i = threadIdx.x; i < n_partials; i += blockDim.x) {
+        anti += partials[i].anti;
+        ups += partials[i].ups;
+    }
+    block_sum2(anti, ups, red);
+    if (threadIdx.x == 0) {
+        int64_t E, M;
+        energy_magnetisation(anti, ups, L, E, M);
+        if (series_E) series_E[idx] = E;
+        if (series_M) series_M[idx] = M;
+        if (out_EM) {
+            out_EM[0] = E;
+            out_EM[1] = M;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_finalize_multi(const LatticeDesc* __restrict__ descs,
+                                                        LatticeState* __restrict__ states,
+                                                        const Partial* __restrict__ partials, uint32_t sweep_off) {
+    __shared__ uint64_t red[32];
+    const LatticeDesc& d = descs[blockIdx.x];
+    if (d.resident || sweep_off >= (uint32_t)d.sweep_limit) return;
+    uint64_t anti = 0, ups = 0;
+    for (int i = threadIdx.x; i < d.part_count; i += blockDim.x) {
+        anti += partials[d.part_begin + i].anti;
+        ups += partials[d.part_begin + i].ups;
+    }
+    block_sum2(anti, ups, red);
+    if (threadIdx.x == 0) {
+        LatticeState& st = states[blockIdx.x];
+        int64_t E, M;
+        energy_magnetisation(anti, ups, d.L, E, M);
+        const int64_t idx = st.series_idx;
+        st.last_E = E;
+        st.last_M = M;
+        st.sum_E += E;
+        st.sum_absM += M < 0 ? -M : M;
+        if (d.series_E) d.series_E[idx] = E;
+        if (d.series_M) d.series_M[idx] = M;
+        st.series_idx = idx + 1;
+        st.n_samples += 1;
+    }
+}
+
+__global__ void k_advance(const LatticeDesc* __restrict__ descs, LatticeState* __restrict__ states, int32_t n,
+                          uint32_t k) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) states[i].t += min(k, (uint32_t)descs[i].sweep_limit);
+}
+
+__global__ void k_reset_sums(LatticeState* __restrict__ states, int32_t n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        states[i].n_samples = 0;
+        states[i].sum_E = 0;
+        states[i].sum_absM = 0;
+    }
+}
+
+__global__ void k_begin_call(LatticeState* __restrict__ states, int32_t n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) states[i].series_idx = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Resident lattices: one workgroup owns a lattice for K sweeps; colours are
+// separated by workgroup barriers.  With IN_LDS the words live in LDS for
+// the whole launch (read once, written once).
+// ---------------------------------------------------------------------------
+template <int WPT, bool IN_LDS>
+__global__ void __launch_bounds__(kResidentMaxBlock)
+    k_resident(const LatticeDesc* __restrict__ descs, LatticeState* __restrict__ states,
+               const int32_t* __restrict__ ids, int32_t K, int32_t every) {
+    extern __shared__ uint64_t lds_words[];
+    __shared__ uint64_t red[32];
+    const int32_t lat = ids[blockIdx.x];
+    const LatticeDesc& d = descs[lat];
+    LatticeState& state = states[lat];
+    const int L = d.L, N = d.N;
+    uint64_t* __restrict__ G = d.W;
+    const uint32_t n_words = (uint32_t)N * (uint32_t)L;
+    if (IN_LDS) {
+        for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x) lds_words[i] = G[i];
+        __syncthreads();
+    }
+    uint64_t* __restrict__ W = IN_LDS ? lds_words : G;
+    auto ld = [&](int i, int j) { return W[i * L + j]; };
+    auto st = [&](int i, int j, uint64_t v) { W[i * L + j] = v; };
+    const int segs = (L + 2 * WPT - 1) / (2 * WPT);
+    const uint32_t units = (uint32_t)N * (uint32_t)segs;
+    const uint64_t t0 = state.t;
+    const int32_t n_sweeps = min(K, d.sweep_limit);
+    // sample accumulators stay in thread 0's registers for the whole launch
+    int64_t series_idx = 0, n_samples = 0, sum_E = 0, sum_absM = 0, last_E = 0, last_M = 0;
+    int64_t* const series_E = d.series_E;
+    int64_t* const series_M = d.series_M;
+    if (threadIdx.x == 0) {
+        series_idx = state.series_idx;
+        n_samples = state.n_samples;
+        sum_E = state.sum_E;
+        sum_absM = state.sum_absM;
+        last_E = state.last_E;
+        last_M = state.last_M;
+    }
+    for (int s = 0; s < n_sweeps; ++s) {
+        const uint64_t t = t0 + (uint64_t)s;
+        const SweepArgs a = {L, N, d.istar, d.sh_star, (uint32_t)t, (uint32_t)(t >> 32), d.k0, d.k1, d.t4, d.t8};
+        const bool meas = every > 0 && ((s + 1) % every) == 0;
+        for (int colour = 0; colour < 2; ++colour) {
+            uint32_t anti = 0, ups = 0;
+            for (uint32_t u = threadIdx.x; u < units; u += blockDim.x) {
+                const int I = (int)(u / (uint32_t)segs);
+                const int seg = (int)(u - (uint32_t)I * (uint32_t)segs);
+                const int J0 = seg * 2 * WPT + ((I + colour) & 1);
+                if (meas && colour == 1) update_segment<WPT, true>(ld, st, I, J0, a, anti, ups);
+                else update_segment<WPT, false>(ld, st, I, J0, a, anti, ups);
+            }
+            __syncthreads();
+            if (meas && colour == 1) {
+                uint64_t A = anti, U = ups;
+                block_sum2(A, U, red);
+                if (threadIdx.x == 0) {
+                    int64_t E, M;
+                    energy_magnetisation(A, U, L, E, M);
+                    last_E = E;
+                    last_M = M;
+                    sum_E += E;
+                    sum_absM += M < 0 ? -M : M;
+                    if (series_E) series_E[series_idx] = E;
+                    if (series_M) series_M[series_idx] = M;
+                    series_idx += 1;
+                    n_samples += 1;
+                }
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        state.series_idx = series_idx;
+        state.n_samples = n_samples;
+        state.sum_E = sum_E;
+        state.sum_absM = sum_absM;
+        state.last_E = last_E;
+        state.last_M = last_M;
+    }
+    if (IN_LDS) {
+        for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x) G[i] = lds_words[i];
+    }
+}
+
+// Observables of every lattice of a table, one workgroup per lattice:
+// antiparallel right and down bonds (Section 5.3) and up spins.
+__global__ void __launch_bounds__(256) k_observe_multi(const LatticeDesc* __restrict__ descs,
+                                                       LatticeState* __restrict__ states,
+                                                       const int32_t* __restrict__ ids) {
+    __shared__ uint64_t red[32];
+    const int32_t lat = ids ? ids[blockIdx.x] : (int32_t)blockIdx.x;
+    const LatticeDesc& d = descs[lat];
+    const int L = d.L, N = d.N;
+    const uint64_t* __restrict__ W = d.W;
+    auto ld = [&](int i, int j) { return W[(size_t)i * L + j]; };
+    uint64_t anti = 0, ups = 0;
+    const uint32_t n_words = (uint32_t)N * (uint32_t)L;
+    for (uint32_t idx = threadIdx.x; idx < n_words; idx += blockDim.x) {
+        const int I = (int)(idx / (uint32_t)L);
+        const int J = (int)(idx - (uint32_t)I * (uint32_t)L);
+        const uint64_t live = live_mask(I, L, N);
+        const uint64_t w = ld(I, J);
+        const uint64_t rt = ld(I, J == L - 1 ? 0 : J + 1);
+        const uint64_t dn = down_word(ld, I, J, N, d.istar, d.sh_star);
+        anti += __popcll((w ^ rt) & live) + __popcll((w ^ dn) & live);
+        ups += __popcll(w & live);
+    }
+    block_sum2(anti, ups, red);
+    if (threadIdx.x == 0) {
+        int64_t E, M;
+        energy_magnetisation(anti, ups, L, E, M);
+        states[lat].last_E = E;
+        states[lat].last_M = M;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_observe_single(const uint64_t* __restrict__ W, Geometry g,
+                                                        Partial* __restrict__ partials) {
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n_words = (uint32_t)g.N * (uint32_t)g.L;
+    uint32_t anti = 0, ups = 0;
+    if (idx < n_words) {
+        const int L = g.L;
+        auto ld = [&](int i, int j) { return W[(size_t)i * L + j]; };
+        const int I = (int)(idx / (uint32_t)L);
+        const int J = (int)(idx - (uint32_t)I * (uint32_t)L);
+        const uint64_t live = live_mask(I, L, g.N);
+        const uint64_t w = ld(I, J);
+        const uint64_t rt = ld(I, J == L - 1 ? 0 : J + 1);
+        const uint64_t dn = down_word(ld, I, J, g.N, g.istar, g.sh_star);
+        anti = __popcll((w ^ rt) & live) + __popcll((w ^ dn) & live);
+        ups = __popcll(w & live);
+    }
+    anti = wave_sum_u32(anti);
+    ups = wave_sum_u32(ups);
+    if (lane_id() == 0) partials[idx >> 6] = {anti, ups};
+}
+
+__global__ void __launch_bounds__(256) k_unpack(const uint64_t* __restrict__ W, Geometry g, int32_t r0, int32_t c0,
+                                                int32_t nrows, int32_t ncols, uint8_t* __restrict__ out) {
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (uint64_t)nrows * (uint64_t)ncols) return;
+    const int i = (int)(idx / (uint64_t)ncols);
+    const int j = (int)(idx - (uint64_t)i * (uint64_t)ncols);
+    const int r = (int)(((int64_t)r0 + i) % g.L);
+    const int c = (int)(((int64_t)c0 + j) % g.L);
+    const int I = r % g.N, p = r / g.N;
+    out[idx] = (uint8_t)((W[(size_t)I * g.L + c] >> (3 * (20 - p))) & 1ull);
+}
+
+__global__ void __launch_bounds__(256) k_pack(const uint8_t* __restrict__ in, Geometry g, uint64_t* __restrict__ W) {
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n_words = (uint32_t)g.N * (uint32_t)g.L;
+    if (idx >= n_words) return;
+    const int I = (int)(idx / (uint32_t)g.L);
+    const int J = (int)(idx - (uint32_t)I * (uint32_t)g.L);
+    uint64_t v = 0;
+    for (int p = 0; p < 21; ++p) {
+        const int64_t r = (int64_t)I + (int64_t)p * g.N;
+        if (r < g.L && in[(size_t)r * g.L + J]) v |= 1ull << (3 * (20 - p));
+    }
+    W[idx] = v;
+}
+
+inline unsigned grid_for(uint64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_init(uint64_t* W, const Geometry& g, uint64_t seed, int hot, hipStream_t s) {
+    const uint64_t n = (uint64_t)g.N * (uint64_t)g.L;
+    hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256)), dim3(256), 0, s, W, g, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), hot);
+    return hipGetLastError();
+}
+
+int64_t halfsweep_single_waves(const Geometry& g, int wpt, int block) {
+    return (int64_t)grid_for((uint64_t)units_per_colour(g, wpt), block) * block / 64;
+}
+
+hipError_t launch_halfsweep_single(int wpt, int block, uint64_t* W, const SweepArgs& a, int colour,
+                                   Partial* partials, int64_t* n_waves, hipStream_t s) {
+    const Geometry g = {a.L, a.N, a.istar, a.sh_star};
+    const int32_t segs = segments_per_row(a.L, wpt);
+    const uint32_t units = (uint32_t)units_per_colour(g, wpt);
+    const dim3 grid(grid_for(units, block)), blk(block);
+    if (n_waves) *n_waves = (int64_t)grid.x * block / 64;
+    const bool m = partials != nullptr;
+#define ISING_LAUNCH_HS(WPT_)                                                                                  \
+    if (m) hipLaunchKernelGGL((k_halfsweep_single<WPT_, true>), grid, blk, 0, s, W, a, segs, units, colour, partials); \
+    else hipLaunchKernelGGL((k_halfsweep_single<WPT_, false>), grid, blk, 0, s, W, a, segs, units, colour, partials);
+    switch (wpt) {
+        case 1: ISING_LAUNCH_HS(1) break;
+        case 2: ISING_LAUNCH_HS(2) break;
+        case 4: ISING_LAUNCH_HS(4) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef ISING_LAUNCH_HS
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_single(const Partial* partials, int64_t n_partials, int32_t L, int64_t* series_E,
+                                  int64_t* series_M, int64_t idx, int64_t* out_EM, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_single, dim3(1), dim3(1024), 0, s, partials, n_partials, L, series_E, series_M,
+                       idx, out_EM);
+    return hipGetLastError();
+}
+
+int64_t observe_single_waves(const Geometry& g) { return (int64_t)grid_for((uint64_t)g.N * g.L, 256) * 4; }
+
+hipError_t launch_observe_single(const uint64_t* W, const Geometry& g, Partial* partials, int64_t* n_waves,
+                                 hipStream_t s) {
+    const uint64_t n = (uint64_t)g.N * (uint64_t)g.L;
+    if (n_waves) *n_waves = (int64_t)grid_for(n, 256) * 4;
+    hipLaunchKernelGGL(k_observe_single, dim3(grid_for(n, 256)), dim3(256), 0, s, W, g, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const uint64_t* W, const Geometry& g, int32_t r0, int32_t c0, int32_t nrows,
+                         int32_t ncols, uint8_t* out, hipStream_t s) {
+    const uint64_t n = (uint64_t)nrows * (uint64_t)ncols;
+    hipLaunchKernelGGL(k_unpack, dim3(grid_for(n, 256)), dim3(256), 0, s, W, g, r0, c0, nrows, ncols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const uint8_t* in, const Geometry& g, uint64_t* W, hipStream_t s) {
+    const uint64_t n = (uint64_t)g.N * (uint64_t)g.L;
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(n, 256)), dim3(256), 0, s, in, g, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, const LatticeState* states,
+                                  const WaveItem* waves, int64_t n_waves, int colour, uint32_t sweep_off,
+                                  Partial* partials, hipStream_t s) {
+    if (n_waves <= 0) return hipSuccess;
+    const dim3 grid(grid_for((uint64_t)n_waves * 64, block)), blk(block);
+    const bool m = partials != nullptr;
+    const uint32_t nw = (uint32_t)n_waves;
+#define ISING_LAUNCH_HM(WPT_)                                                                                       \
+    if (m) hipLaunchKernelGGL((k_halfsweep_multi<WPT_, true>), grid, blk, 0, s, descs, states, waves, nw, colour,  \
+                              sweep_off, partials);                                                                 \
+    else hipLaunchKernelGGL((k_halfsweep_multi<WPT_, false>), grid, blk, 0, s, descs, states, waves, nw, colour,   \
+                            sweep_off, partials);
+    switch (wpt) {
+        case 1: ISING_LAUNCH_HM(1) break;
+        case 2: ISING_LAUNCH_HM(2) break;
+        case 4: ISING_LAUNCH_HM(4) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef ISING_LAUNCH_HM
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_multi(const LatticeDesc* descs, LatticeState* states, int32_t n_lat,
+                                 const Partial* partials, uint32_t sweep_off, hipStream_t s) {
+    if (n_lat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_multi, dim3(n_lat), dim3(256), 0, s, descs, states, partials, sweep_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(const LatticeDesc* descs, LatticeState* states, int32_t n_lat, uint32_t k, hipStream_t s) {
+    if (n_lat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_advance, dim3(grid_for(n_lat, 256)), dim3(256), 0, s, descs, states, n_lat, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_sums(LatticeState* states, int32_t n_lat, hipStream_t s) {
+    if (n_lat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reset_sums, dim3(grid_for(n_lat, 256)), dim3(256), 0, s, states, n_lat);
+    return hipGetLastError();
+}
+
+hipError_t launch_begin_call(LatticeState* states, int32_t n_lat, hipStream_t s) {
+    if (n_lat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_begin_call, dim3(grid_for(n_lat, 256)), dim3(256), 0, s, states, n_lat);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe_multi(const LatticeDesc* descs, LatticeState* states, const int32_t* ids, int32_t n_lat,
+                                hipStream_t s) {
+    if (n_lat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_observe_multi, dim3(n_lat), dim3(256), 0, s, descs, states, ids);
+    return hipGetLastError();
+}
+
+size_t resident_lds_limit(int device) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) return 0;
+    const size_t static_bytes = 32 * sizeof(uint64_t) + 64;
+    return v > (int)static_bytes ? (size_t)v - static_bytes : 0;
+}
+
+hipError_t set_resident_lds(int wpt, size_t lds_bytes) {
+    const void* f = wpt == 1 ? reinterpret_cast<const void*>(&k_resident<1, true>)
+                  : wpt == 2 ? reinterpret_cast<const void*>(&k_resident<2, true>)
+                             : reinterpret_cast<const void*>(&k_resident<4, true>);
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
+hipError_t launch_resident(int wpt, int block, const LatticeDesc* descs, LatticeState* states, const int32_t* ids,
+                           int32_t n_ids, int32_t K, int32_t every, size_t lds_bytes, hipStream_t s) {
+    if (n_ids <= 0 || K <= 0) return hipSuccess;
+    if (block < 64 || block > kResidentMaxBlock || block % 64) return hipErrorInvalidValue;
+    const dim3 grid(n_ids), blk(block);
+#define ISING_LAUNCH_RES(WPT_)                                                                                  \
+    if (lds_bytes > 0) {                                                                                        \
+        hipLaunchKernelGGL((k_resident<WPT_, true>), grid, blk, lds_bytes, s, descs, states, ids, K, every);    \
+    } else {                                                                                                    \
+        hipLaunchKernelGGL((k_resident<WPT_, false>), grid, blk, 0, s, descs, states, ids, K, every);           \
+    }
+    switch (wpt) {
+        case 1: ISING_LAUNCH_RES(1) break;
+        case 2: ISING_LAUNCH_RES(2) break;
+        case 4: ISING_LAUNCH_RES(4) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef ISING_LAUNCH_RES
+    return hipGetLastError();
+}
+
+}  // namespace ising

@@ -1,0 +1,338 @@
+// C ABI of the single-lattice path: one lattice, two half-sweep launches per
+// sweep on the caller's stream (the plain one-lattice-per-launch form).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ising_host.hpp"
+#include "ising_launch.hpp"
+
+using namespace ising;
+
+struct ising_lattice {
+    Geometry g;
+    uint64_t seed = 0;
+    uint64_t t = 0;  // absolute index of the next sweep
+    uint64_t* W = nullptr;
+    bool owns_W = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int wpt = 4;
+    int block = 256;
+    Partial* partials = nullptr;  // per-wavefront bond/spin counts
+    int64_t partial_cap = 0;
+    int64_t* d_EM = nullptr;  // device scratch: E, M of ising_observables
+};
+
+namespace ising {
+std::string& last_error_ref() {
+    thread_local std::string s;
+    return s;
+}
+}  // namespace ising
+
+extern "C" {
+
+const char* ising_last_error(void) { return last_error_ref().c_str(); }
+
+const char* ising_version(void) { return "ising-msc 1.0 (gfx950)"; }
+
+int32_t ising_word_rows(int32_t L) { return valid_L(L) ? make_geometry(L).N : 0; }
+
+size_t ising_required_bytes(int32_t L) {
+    if (!valid_L(L)) return 0;
+    const Geometry g = make_geometry(L);
+    return (size_t)g.N * (size_t)g.L * sizeof(uint64_t);
+}
+
+int ising_thresholds(double T, uint32_t* t4, uint32_t* t8) {
+    if (!valid_T(T)) return fail(ISING_EINVAL, "ising_thresholds: T must be finite and > 0 (got %g)", T);
+    if (!t4 || !t8) return fail(ISING_EINVAL, "ising_thresholds: null output");
+    thresholds_of(T, t4, t8);
+    return ISING_OK;
+}
+
+static int64_t partials_needed(const Geometry& g) {
+    // largest number of wavefronts any allowed plan launches
+    int64_t m = observe_single_waves(g);
+    for (int wpt : {1, 2, 4})
+        for (int block = 64; block <= 256; block += 64) m = std::max(m, halfsweep_single_waves(g, wpt, block));
+    return m;
+}
+
+static void release(ising_lattice* h) {
+    if (!h) return;
+    if (h->owns_W && h->W) (void)hipFree(h->W);
+    if (h->partials) (void)hipFree(h->partials);
+    if (h->d_EM) (void)hipFree(h->d_EM);
+    delete h;
+}
+
+static int create_impl(int32_t L, uint64_t seed, int32_t init, void* dev_words, size_t bytes, void* stream,
+                       ising_lattice** out) {
+    if (!out) return fail(ISING_EINVAL, "ising_create: null output handle");
+    *out = nullptr;
+    if (!valid_L(L)) return fail(ISING_EINVAL, "ising_create: L must be even and in [4, %d] (got %d)", kMaxL, L);
+    if (init != ISING_COLD && init != ISING_HOT) return fail(ISING_EINVAL, "ising_create: init must be 0 or 1");
+    const size_t need = ising_required_bytes(L);
+    if (dev_words) {
+        if (bytes < need) return fail(ISING_EINVAL, "ising_create_in: buffer of %zu bytes < %zu needed", bytes, need);
+        if (reinterpret_cast<uintptr_t>(dev_words) % 8) return fail(ISING_EINVAL, "ising_create_in: buffer not 8-byte aligned");
+    }
+    ising_lattice* h = new (std::nothrow) ising_lattice();
+    if (!h) return fail(ISING_ENOMEM, "ising_create: host allocation failed");
+    h->g = make_geometry(L);
+    h->seed = seed;
+    h->stream = (hipStream_t)stream;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        release(h);
+        return hip_fail(e, "hipGetDevice");
+    }
+    if (dev_words) {
+        h->W = (uint64_t*)dev_words;
+    } else {
+        e = hipMalloc(&h->W, need);
+        if (e != hipSuccess) {
+            h->W = nullptr;
+            release(h);
+            return fail(ISING_ENOMEM, "ising_create: hipMalloc of %zu bytes failed: %s", need, hipGetErrorString(e));
+        }
+        h->owns_W = true;
+    }
+    h->partial_cap = partials_needed(h->g);
+    e = hipMalloc(&h->partials, (size_t)h->partial_cap * sizeof(Partial));
+    if (e == hipSuccess) e = hipMalloc(&h->d_EM, 2 * sizeof(int64_t));
+    if (e != hipSuccess) {
+        release(h);
+        return fail(ISING_ENOMEM, "ising_create: scratch allocation failed: %s", hipGetErrorString(e));
+    }
+    // default plan: four words per thread unless that leaves the chip idle
+    h->wpt = units_per_colour(h->g, 4) >= 64 * 1024 ? 4 : (units_per_colour(h->g, 2) >= 64 * 1024 ? 2 : 1);
+    h->block = 256;
+    e = launch_init(h->W, h->g, seed, init, h->stream);
+    if (e != hipSuccess) {
+        release(h);
+        return hip_fail(e, "init kernel launch");
+    }
+    *out = h;
+    return ISING_OK;
+}
+
+int ising_create(int32_t L, uint64_t seed, int32_t init, void* stream, ising_lattice** out) {
+    return create_impl(L, seed, init, nullptr, 0, stream, out);
+}
+
+int ising_create_in(int32_t L, uint64_t seed, int32_t init, void* dev_words, size_t bytes, void* stream,
+                    ising_lattice** out) {
+    if (!dev_words) return fail(ISING_EINVAL, "ising_create_in: null device buffer");
+    return create_impl(L, seed, init, dev_words, bytes, stream, out);
+}
+
+int ising_destroy(ising_lattice* h) {
+    if (!h) return ISING_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    release(h);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return ISING_OK;
+}
+
+static SweepArgs sweep_args(const ising_lattice* h, uint64_t t, uint32_t t4, uint32_t t8) {
+    SweepArgs a;
+    a.L = h->g.L;
+    a.N = h->g.N;
+    a.istar = h->g.istar;
+    a.sh_star = h->g.sh_star;
+    a.t_lo = (uint32_t)t;
+    a.t_hi = (uint32_t)(t >> 32);
+    a.k0 = (uint32_t)h->seed;
+    a.k1 = (uint32_t)(h->seed >> 32);
+    a.t4 = t4;
+    a.t8 = t8;
+    return a;
+}
+
+// Enqueue n sweeps of lattice words W (the handle's or a scratch copy)
+// starting at absolute sweep t0.
+static int enqueue_sweeps(const ising_lattice* h, uint64_t* W, uint64_t t0, double T, int64_t n, int32_t every,
+                          int64_t* dev_E, int64_t* dev_M, int wpt, int block) {
+    uint32_t t4, t8;
+    thresholds_of(T, &t4, &t8);
+    for (int64_t k = 1; k <= n; ++k) {
+        const SweepArgs a = sweep_args(h, t0 + (uint64_t)(k - 1), t4, t8);
+        ISING_HIP(launch_halfsweep_single(wpt, block, W, a, 0, nullptr, nullptr, h->stream));
+        const bool meas = every > 0 && k % every == 0;
+        int64_t nw = 0;
+        ISING_HIP(launch_halfsweep_single(wpt, block, W, a, 1, meas ? h->partials : nullptr, &nw, h->stream));
+        if (meas)
+            ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, dev_E, dev_M, k / every - 1, nullptr, h->stream));
+    }
+    return ISING_OK;
+}
+
+static int sweep_impl(ising_lattice* h, double T, int64_t n, int32_t every, int64_t* dev_E, int64_t* dev_M) {
+    if (!h) return fail(ISING_EINVAL, "ising_sweep: null handle");
+    if (!valid_T(T)) return fail(ISING_EINVAL, "ising_sweep: T must be finite and > 0 (got %g)", T);
+    if (n < 0) return fail(ISING_EINVAL, "ising_sweep: n_sweeps must be >= 0");
+    int rc = enqueue_sweeps(h, h->W, h->t, T, n, every, dev_E, dev_M, h->wpt, h->block);
+    if (rc != ISING_OK) return rc;
+    h->t += (uint64_t)n;
+    return ISING_OK;
+}
+
+int ising_sweep(ising_lattice* h, double T, int64_t n_sweeps) { return sweep_impl(h, T, n_sweeps, 0, nullptr, nullptr); }
+
+int ising_sweep_measure(ising_lattice* h, double T, int64_t n_sweeps, int32_t every, int64_t* dev_E,
+                        int64_t* dev_M) {
+    if (every < 1) return fail(ISING_EINVAL, "ising_sweep_measure: every must be >= 1");
+    if (!dev_E || !dev_M) return fail(ISING_EINVAL, "ising_sweep_measure: null series pointer");
+    return sweep_impl(h, T, n_sweeps, every, dev_E, dev_M);
+}
+
+int ising_observables(ising_lattice* h, int64_t* E, int64_t* M) {
+    if (!h || !E || !M) return fail(ISING_EINVAL, "ising_observables: null argument");
+    int64_t nw = 0;
+    ISING_HIP(launch_observe_single(h->W, h->g, h->partials, &nw, h->stream));
+    ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, nullptr, nullptr, 0, h->d_EM, h->stream));
+    int64_t em[2];
+    ISING_HIP(hipMemcpyAsync(em, h->d_EM, sizeof em, hipMemcpyDeviceToHost, h->stream));
+    ISING_HIP(hipStreamSynchronize(h->stream));
+    *E = em[0];
+    *M = em[1];
+    return ISING_OK;
+}
+
+int ising_get_spins_region(ising_lattice* h, int32_t r0, int32_t c0, int32_t nrows, int32_t ncols, uint8_t* host) {
+    if (!h || !host) return fail(ISING_EINVAL, "ising_get_spins_region: null argument");
+    const int32_t L = h->g.L;
+    if (nrows < 1 || ncols < 1 || nrows > L || ncols > L)
+        return fail(ISING_EINVAL, "ising_get_spins_region: window %dx%d outside 1..L=%d", nrows, ncols, L);
+    const int32_t rr = (int32_t)(((int64_t)r0 % L + L) % L), cc = (int32_t)(((int64_t)c0 % L + L) % L);
+    const size_t bytes = (size_t)nrows * (size_t)ncols;
+    uint8_t* d = nullptr;
+    ISING_HIP(hipMalloc(&d, bytes));
+    hipError_t e = launch_unpack(h->W, h->g, rr, cc, nrows, ncols, d, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    hipError_t e2 = hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "ising_get_spins_region");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
+    return ISING_OK;
+}
+
+int ising_get_spins(ising_lattice* h, uint8_t* host) {
+    if (!h) return fail(ISING_EINVAL, "ising_get_spins: null handle");
+    return ising_get_spins_region(h, 0, 0, h->g.L, h->g.L, host);
+}
+
+int ising_set_spins(ising_lattice* h, const uint8_t* host) {
+    if (!h || !host) return fail(ISING_EINVAL, "ising_set_spins: null argument");
+    const size_t bytes = (size_t)h->g.L * (size_t)h->g.L;
+    uint8_t* d = nullptr;
+    ISING_HIP(hipMalloc(&d, bytes));
+    hipError_t e = hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_pack(d, h->g, h->W, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    hipError_t e2 = hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "ising_set_spins");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
+    return ISING_OK;
+}
+
+int ising_get_sweep_count(ising_lattice* h, uint64_t* t) {
+    if (!h || !t) return fail(ISING_EINVAL, "ising_get_sweep_count: null argument");
+    *t = h->t;
+    return ISING_OK;
+}
+
+int ising_set_sweep_count(ising_lattice* h, uint64_t t) {
+    if (!h) return fail(ISING_EINVAL, "ising_set_sweep_count: null handle");
+    h->t = t;
+    return ISING_OK;
+}
+
+int ising_words(ising_lattice* h, void** dev_words, size_t* bytes) {
+    if (!h || !dev_words || !bytes) return fail(ISING_EINVAL, "ising_words: null argument");
+    *dev_words = h->W;
+    *bytes = ising_required_bytes(h->g.L);
+    return ISING_OK;
+}
+
+int ising_set_plan(ising_lattice* h, int32_t wpt, int32_t block) {
+    if (!h) return fail(ISING_EINVAL, "ising_set_plan: null handle");
+    if (wpt != 1 && wpt != 2 && wpt != 4) return fail(ISING_EINVAL, "ising_set_plan: words_per_thread must be 1, 2 or 4");
+    if (!valid_block(block, 256)) return fail(ISING_EINVAL, "ising_set_plan: block must be 64, 128, 192 or 256");
+    h->wpt = wpt;
+    h->block = block;
+    return ISING_OK;
+}
+
+int ising_get_plan(ising_lattice* h, int32_t* wpt, int32_t* block) {
+    if (!h || !wpt || !block) return fail(ISING_EINVAL, "ising_get_plan: null argument");
+    *wpt = h->wpt;
+    *block = h->block;
+    return ISING_OK;
+}
+
+int ising_synchronize(ising_lattice* h) {
+    if (!h) return fail(ISING_EINVAL, "ising_synchronize: null handle");
+    ISING_HIP(hipStreamSynchronize(h->stream));
+    return ISING_OK;
+}
+
+int ising_autotune(ising_lattice* h, double T, double* best_ms_per_sweep) {
+    if (!h) return fail(ISING_EINVAL, "ising_autotune: null handle");
+    if (!valid_T(T)) return fail(ISING_EINVAL, "ising_autotune: T must be finite and > 0");
+    const size_t bytes = ising_required_bytes(h->g.L);
+    uint64_t* scratch = nullptr;
+    ISING_HIP(hipMalloc(&scratch, bytes));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = ISING_OK;
+    double best = 1e300;
+    int best_wpt = h->wpt, best_block = h->block;
+    const double work = (double)h->g.L * (double)h->g.L;
+    const int64_t n_time = std::max<int64_t>(2, std::min<int64_t>(50, (int64_t)(2e9 / work)));
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemcpyAsync(scratch, h->W, bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "ising_autotune setup");
+    const int wpts[3] = {1, 2, 4};
+    const int blocks[3] = {64, 128, 256};
+    for (int wi = 0; wi < 3 && rc == ISING_OK; ++wi) {
+        for (int bi = 0; bi < 3 && rc == ISING_OK; ++bi) {
+            rc = enqueue_sweeps(h, scratch, h->t, T, 1, 0, nullptr, nullptr, wpts[wi], blocks[bi]);  // warm-up
+            if (rc != ISING_OK) break;
+            e = hipEventRecord(e0, h->stream);
+            if (e == hipSuccess) rc = enqueue_sweeps(h, scratch, h->t, T, n_time, 0, nullptr, nullptr, wpts[wi], blocks[bi]);
+            if (rc != ISING_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "ising_autotune timing");
+                break;
+            }
+            const double per = ms / (double)n_time;
+            if (per < best) {
+                best = per;
+                best_wpt = wpts[wi];
+                best_block = blocks[bi];
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(scratch);
+    if (rc != ISING_OK) return rc;
+    h->wpt = best_wpt;
+    h->block = best_block;
+    if (best_ms_per_sweep) *best_ms_per_sweep = best;
+    return ISING_OK;
+}
+
+}  // extern "C"

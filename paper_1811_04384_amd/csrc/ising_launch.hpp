@@ -1,0 +1,77 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ising_common.hpp"
+
+namespace ising {
+
+// Tiled work of one colour of a lattice: segments of 2*wpt columns per row.
+inline int32_t segments_per_row(int32_t L, int32_t wpt) { return (L + 2 * wpt - 1) / (2 * wpt); }
+inline int64_t units_per_colour(const Geometry& g, int32_t wpt) {
+    return (int64_t)g.N * segments_per_row(g.L, wpt);
+}
+
+// Spins of a fresh lattice: cold (all up) or hot (Philox stream 0 draw < 2^31).
+hipError_t launch_init(uint64_t* W, const Geometry& g, uint64_t seed, int hot, hipStream_t s);
+
+// One half-sweep of one lattice (colour 0 or 1).  With `partials` non-null
+// (colour 1 only) every wavefront stores its bond/spin counts in
+// partials[wave]; the number of launched wavefronts (the slots written) is
+// returned in *n_waves.
+hipError_t launch_halfsweep_single(int wpt, int block, uint64_t* W, const SweepArgs& a, int colour,
+                                   Partial* partials, int64_t* n_waves, hipStream_t s);
+int64_t halfsweep_single_waves(const Geometry& g, int wpt, int block);
+
+// Sum the partials of one lattice into E, M and store them: sample index
+// `idx` of series (if non-null), and out_EM[0..1] (if non-null).
+hipError_t launch_finalize_single(const Partial* partials, int64_t n_partials, int32_t L, int64_t* series_E,
+                                  int64_t* series_M, int64_t idx, int64_t* out_EM, hipStream_t s);
+
+// Observables of one lattice: per-wavefront partials of right+down
+// antiparallel bonds and up spins over all words.
+hipError_t launch_observe_single(const uint64_t* W, const Geometry& g, Partial* partials, int64_t* n_waves,
+                                 hipStream_t s);
+int64_t observe_single_waves(const Geometry& g);
+
+// Unpack an nrows x ncols window (indices mod L) to bytes; pack a full byte
+// lattice into words.
+hipError_t launch_unpack(const uint64_t* W, const Geometry& g, int32_t r0, int32_t c0, int32_t nrows,
+                         int32_t ncols, uint8_t* out, hipStream_t s);
+hipError_t launch_pack(const uint8_t* in, const Geometry& g, uint64_t* W, hipStream_t s);
+
+// ---- batches --------------------------------------------------------------
+
+// Tiled half-sweep over a wave table covering many lattices.
+hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, const LatticeState* states,
+                                  const WaveItem* waves, int64_t n_waves, int colour, uint32_t sweep_off,
+                                  Partial* partials, hipStream_t s);
+// Per-lattice finalize of a measured sweep for the tiled lattices.
+// Lattices whose sweep_limit is <= sweep_off took no part in that sweep and
+// are skipped.
+hipError_t launch_finalize_multi(const LatticeDesc* descs, LatticeState* states, int32_t n_lat,
+                                 const Partial* partials, uint32_t sweep_off, hipStream_t s);
+// t += min(k, sweep_limit) for every lattice.
+hipError_t launch_advance(const LatticeDesc* descs, LatticeState* states, int32_t n_lat, uint32_t k, hipStream_t s);
+// One workgroup per listed lattice, K sweeps per launch; samples after local
+// sweeps s with (s + 1) % every == 0 (every > 0).  lds_bytes > 0 keeps the
+// lattice in LDS (it must fit; call set_resident_lds first, outside any
+// graph capture).
+hipError_t set_resident_lds(int wpt, size_t lds_bytes);
+hipError_t launch_resident(int wpt, int block, const LatticeDesc* descs, LatticeState* states, const int32_t* ids,
+                           int32_t n_ids, int32_t K, int32_t every, size_t lds_bytes, hipStream_t s);
+// Current E and M into states[i].last_E / last_M for the lattices ids[0..n)
+// (ids null: lattices 0..n).
+hipError_t launch_observe_multi(const LatticeDesc* descs, LatticeState* states, const int32_t* ids, int32_t n_lat,
+                                hipStream_t s);
+// Zero the sample accumulators of every lattice; start a call (series_idx = 0).
+hipError_t launch_reset_sums(LatticeState* states, int32_t n_lat, hipStream_t s);
+hipError_t launch_begin_call(LatticeState* states, int32_t n_lat, hipStream_t s);
+
+// Largest dynamic LDS a resident workgroup may use on this device.
+size_t resident_lds_limit(int device);
+
+}  // namespace ising
