@@ -1,0 +1,397 @@
+#!/usr/bin/env python3
+"""Benchmark of the multi-spin-coded checkerboard Metropolis sweep on one MI355X.
+
+Headline workload (one "step"): a single L = 32768 lattice (1.07e9 spins,
+409.5 MB packed at 21 spins per uint64), hot start with seed 11, run at each
+of T = 2.0, 2.269, 2.6 for 2000 sweeps from a fresh start, final E and M read
+back -- 3 x 2000 x 32768^2 = 6.44e12 spin-flip attempts per step.  Inputs are
+synthetic (generated on the device from the seed); the lattice buffer is
+allocated before the timed region.
+
+Printed: ONE JSON line with the contract fields, a `roofline` object for the
+dominant kernel (the half-sweep kernel, integer-ALU bound), a `cpu_baseline`
+object (the CPU oracle on a bounded sample of the same workload) and a
+`secondary` object with the other workloads: the plain one-lattice-per-launch
+L = 4096 run, the batched mixed-L run, the L = 64 temperature scan and a
+served request stream with p50/p99 latency.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "spin-flip attempts/ns (L=32768 single; batched mixed-L) + p50/p99 latency"
+UNIT = "attempts/ns"
+
+# Integer-ALU roofline: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
+# single-slot 32-bit lane operations per second, the rate that gives the
+# published 157.3 TFLOP/s FP32 vector peak when a lane op is an FMA.
+ALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+# Algorithmic integer lane-op slots per spin-flip attempt: a quarter of one
+# Philox4x32-10 block (10 rounds x (2 wide 32x32->64 products at 2 slots
+# each + 2 three-input XORs) = 60 slots per block -> 15), two threshold
+# comparisons, and one slot for the bit-sliced neighbour count and flip.
+OPS_PER_ATTEMPT = 18.0
+HBM_PEAK_GBS = 8000.0
+
+L_MAIN, SEED_MAIN, TEMPS_MAIN, SWEEPS_MAIN = 32768, 11, (2.0, 2.269, 2.6), 2000
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _events():
+    import torch
+
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def run_main(ising, steps, warmup, sweeps):
+    import torch
+
+    lat = ising.Lattice(L_MAIN, SEED_MAIN, hot=True)
+    wpt, block = lat.plan()
+    results = []
+    loop_ms = []
+
+    def one_step(record):
+        out = []
+        for T in TEMPS_MAIN:
+            lat.reset(SEED_MAIN, hot=True)
+            e0, e1 = _events()
+            e0.record()
+            lat.sweep(T, sweeps)
+            e1.record()
+            E, M = lat.observables()  # synchronises the stream
+            if record:
+                loop_ms.append(e0.elapsed_time(e1))
+            out.append({"T": T, "E": E, "M": M, "e_per_spin": E / L_MAIN ** 2, "m_per_spin": M / L_MAIN ** 2})
+        return out
+
+    for _ in range(warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        results = one_step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.close()
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    attempts = len(TEMPS_MAIN) * sweeps * L_MAIN ** 2
+    launches = 2 * sweeps * len(TEMPS_MAIN) * steps
+    avg_launch_ms = sum(loop_ms) / launches
+    return {
+        "ms_per_step": ms_per_step,
+        "value": attempts / (ms_per_step * 1e6),
+        "avg_halfsweep_ms": avg_launch_ms,
+        "plan": {"words_per_thread": wpt, "block": block},
+        "final": results,
+    }
+
+
+def roofline(avg_halfsweep_ms, traffic):
+    attempts_per_launch = L_MAIN ** 2 / 2
+    achieved = OPS_PER_ATTEMPT * attempts_per_launch / (avg_halfsweep_ms * 1e-3) / 1e12
+    return {
+        "bound": "alu",
+        "achieved": round(achieved, 2),
+        "peak": round(ALU_PEAK_TOPS, 2),
+        "unit": "Tops/s",
+        "frac": round(achieved / ALU_PEAK_TOPS, 4),
+        "traffic": traffic,
+        "kernel": "k_halfsweep_single",
+        "ops_per_attempt": OPS_PER_ATTEMPT,
+        "attempts_per_launch": attempts_per_launch,
+        "avg_launch_ms": round(avg_halfsweep_ms, 5),
+        "hbm_gbs_algorithmic": round(1.5 * 8 * ising_words_main() / (avg_halfsweep_ms * 1e-3) / 1e9, 1),
+    }
+
+
+def ising_words_main():
+    n = (L_MAIN + 20) // 21
+    n += n & 1
+    return n * L_MAIN
+
+
+def load_traffic():
+    """HBM bytes per half-sweep launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration),
+    or None if the summary is missing."""
+    path = os.path.join(ROOT, "profiles", "halfsweep_L32768_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return {"bytes_per_launch": d["bytes_per_launch"], "source": "profiles/halfsweep_L32768_traffic.json",
+                "algorithmic_bytes_per_launch": d.get("algorithmic_bytes_per_launch")}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(target_s=12.0):
+    """The CPU oracle on a bounded sample of the headline workload: a
+    4096 x 4096 window of the L = 32768 hot-start lattice (seed 11) evolved
+    at T = 2.269 for as many sweeps as fit in about target_s seconds (the
+    per-site work is the same as on the full lattice)."""
+    import oracle
+
+    L, seed, T, w = L_MAIN, SEED_MAIN, 2.269, 4096
+    win = oracle.init_window(L, seed, True, 0, 0, w, w)
+    threads = oracle.max_threads()
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < target_s:
+        oracle.sweep_window(win, L, seed, done, 2, T, 0, 0)
+        done += 2
+    dt = time.perf_counter() - t0
+    attempts = done * (w - 2) * (w - 2)  # sites updated per sweep: the window minus its border
+    return {"value": round(attempts / (dt * 1e9), 5), "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"{w}x{w} window of the L=32768 hot-start lattice (seed 11), T=2.269, {done} sweeps, "
+                      f"{dt:.1f} s on {threads} threads"}
+
+
+# ---------------------------------------------------------------------------
+# secondary workloads
+# ---------------------------------------------------------------------------
+
+def run_plain4096(ising, sweeps=10000, every=10):
+    """Single lattice L=4096, hot start seed 7, T=2.269, E/M every 10 sweeps,
+    one lattice per launch (the plain form)."""
+    import torch
+
+    lat = ising.Lattice(4096, 7, hot=True)
+    lat.sweep_measure(2.269, 100, every)
+    lat.reset(7, hot=True)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    E, M = lat.sweep_measure(2.269, sweeps, every)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    e = E.double().mean().item() / 4096 ** 2
+    lat.close()
+    return {"workload": "L=4096 single, hot seed 7, T=2.269, 10000 sweeps, E/M every 10",
+            "value": round(4096 ** 2 * sweeps / (ms * 1e6), 2), "unit": UNIT, "ms": round(ms, 2),
+            "mean_e_per_spin": round(e, 6)}
+
+
+def batched_config():
+    Ls = [(256, 512, 1024, 2048)[i % 4] for i in range(2048)]
+    Ts = [1.5 + 2.0 * ((i // 4) % 32) / 31 for i in range(2048)]
+    seeds = list(range(2048))
+    return Ls, Ts, seeds
+
+
+def run_batched(ising, sweeps=5000, every=10):
+    """2048 lattices, L in {256, 512, 1024, 2048} (512 each), 32 temperatures
+    over [1.5, 3.5], hot start seed = index, 5000 sweeps, E/M every 10; the
+    plan from the autotuner, chunks replayed as hipGraphs."""
+    import torch
+
+    Ls, Ts, seeds = batched_config()
+    b = ising.Batch(Ls, seeds, hot=True)
+    cache = os.path.join(os.path.expanduser("~"), ".cache", "ising_msc", "tune.json")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    t_tune = time.perf_counter()
+    plan = b.autotune(Ts, cache)
+    t_tune = time.perf_counter() - t_tune
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    b.sweep(Ts, sweeps, every=every)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    res = b.results()
+    spins = sum(L * L for L in Ls)
+    b.close()
+    return {"workload": "2048 lattices L in {256,512,1024,2048}, 32 T in [1.5,3.5], hot, 5000 sweeps, E/M every 10",
+            "value": round(spins * sweeps / (ms * 1e6), 2), "unit": UNIT, "ms": round(ms, 1), "plan": plan,
+            "autotune_s": round(t_tune, 2), "samples_per_lattice": int(res["n_samples"][0])}
+
+
+def run_scan64(ising, therm=2000, meas=2000):
+    """L=64, cold start, 8 temperatures over [1.5, 3.5], seed 1234, 2000 + 2000
+    sweeps (sample every measured sweep): batched (one workgroup per lattice,
+    LDS-resident) and as 8 plain lattices."""
+    import torch
+
+    Ts = [1.5 + 2.0 * i / 7 for i in range(8)]
+    b = ising.Batch([64] * 8, [1234] * 8, hot=False)
+    b.set_plan(resident_max_L=64, resident_block=64, words_per_thread=1, tiled_block=256, sweeps_per_graph=500)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    b.sweep(Ts, therm)
+    b.sweep(Ts, meas, every=1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    res = b.results()
+    b.close()
+    mean_e = [round(float(s) / n / 64 ** 2, 5) for s, n in zip(res["sum_E"], res["n_samples"])]
+    mean_m = [round(float(s) / n / 64 ** 2, 5) for s, n in zip(res["sum_absM"], res["n_samples"])]
+    lats = [ising.Lattice(64, 1234, hot=False) for _ in Ts]
+    torch.cuda.synchronize()
+    e0.record()
+    for lat, T in zip(lats, Ts):
+        lat.sweep(T, therm)
+        lat.sweep_measure(T, meas, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1)
+    for lat in lats:
+        lat.close()
+    att = 8 * 64 * 64 * (therm + meas)
+    return {"workload": "8 x L=64 cold, seed 1234, T=1.5..3.5, 2000+2000 sweeps",
+            "batched_value": round(att / (ms_b * 1e6), 3), "plain_value": round(att / (ms_p * 1e6), 3),
+            "unit": UNIT, "mean_e_per_spin": mean_e, "mean_absm_per_spin": mean_m}
+
+
+def run_serving(ising, rate=25.0, duration=10.0, quantum=100, seed=2026):
+    """Poisson request stream: L = 2^U{7..12}, T ~ U[1.5, 3.5], sweeps ~
+    U{1000..20000}, hot start with seed = request id; continuous batching."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    arrivals = []
+    t = 0.0
+    rid = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration:
+            break
+        arrivals.append((t, rid, int(2 ** rng.integers(7, 13)), float(rng.uniform(1.5, 3.5)),
+                         int(rng.integers(1000, 20001))))
+        rid += 1
+    srv = ising.Server(hbm_budget=16 << 30, max_slots=8192, quantum_sweeps=quantum)
+    lat_s = []
+    attempts = 0
+    i = 0
+    t0 = time.perf_counter()
+    done = 0
+    while done < len(arrivals):
+        now = time.perf_counter() - t0
+        while i < len(arrivals) and arrivals[i][0] <= now:
+            _, r, L, T, sw = arrivals[i]
+            srv.submit(r, L, T, sw)
+            i += 1
+        active = srv.step()
+        for r in srv.poll():
+            lat_s.append(r["t_done_s"] - r["t_submit_s"])
+            attempts += r["L"] * r["L"] * r["sweeps"]
+            done += 1
+        if active == 0 and i < len(arrivals):
+            time.sleep(max(0.0, min(0.01, arrivals[i][0] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.sort(np.array(lat_s))
+    return {"workload": f"Poisson {rate:g} req/s for {duration:g} s, L=2^U{{7..12}}, T~U[1.5,3.5], "
+                        f"sweeps~U{{1000..20000}}, quantum {quantum}",
+            "requests": len(arrivals), "p50_s": round(float(np.percentile(lat, 50)), 3),
+            "p99_s": round(float(np.percentile(lat, 99)), 3), "throughput_req_s": round(len(arrivals) / wall, 2),
+            "value": round(attempts / (wall * 1e9), 2), "unit": UNIT, "wall_s": round(wall, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sweeps", type=int, default=SWEEPS_MAIN, help="sweeps per temperature (headline: 2000)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--secondary", default="plain4096,batched,scan64,serving",
+                    help="comma list of secondary workloads, or 'none'")
+    ap.add_argument("--serving-rate", type=float, default=25.0)
+    ap.add_argument("--serving-duration", type=float, default=10.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run 10 device-to-device copies of BYTES bytes (HBM counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the lattice kernels run on a single MI355X and this build has no "
+              "multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1811_04384_amd as ising
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    ising.load()
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe // 4, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 10}), flush=True)
+        return
+
+    log(f"headline: L={L_MAIN} x T={TEMPS_MAIN} x {args.sweeps} sweeps, warmup {args.warmup}, steps {args.steps}")
+    main_res = run_main(ising, args.steps, args.warmup, args.sweeps)
+    log(f"headline: {main_res['value']:.1f} attempts/ns, {main_res['ms_per_step']:.1f} ms/step")
+    traffic = load_traffic()
+
+    secondary = {}
+    wanted = [] if args.secondary == "none" else args.secondary.split(",")
+    for name in wanted:
+        log(f"secondary: {name}")
+        if name == "plain4096":
+            secondary[name] = run_plain4096(ising)
+        elif name == "batched":
+            secondary[name] = run_batched(ising)
+        elif name == "scan64":
+            secondary[name] = run_scan64(ising)
+        elif name == "serving":
+            secondary[name] = run_serving(ising, args.serving_rate, args.serving_duration)
+        log(f"  {secondary.get(name)}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": METRIC,
+        "value": round(main_res["value"], 2),
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (Philox hot start on the device)",
+        "config": {
+            "workload": f"single lattice L=32768, hot start seed 11, T in {{2.0, 2.269, 2.6}}, "
+                        f"{args.sweeps} sweeps each, final E/M",
+            "L": L_MAIN, "temperatures": list(TEMPS_MAIN), "sweeps_per_T": args.sweeps, "seed": SEED_MAIN,
+            "plan": main_res["plan"], "parallelism": "single GPU",
+        },
+        "roofline": roofline(main_res["avg_halfsweep_ms"], traffic),
+        "cpu_baseline": cpu,
+        "final_observables": main_res["final"],
+        "secondary": secondary,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

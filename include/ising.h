@@ -114,6 +114,11 @@ int ising_create(int32_t L, uint64_t seed, int32_t init, void* stream, ising_lat
 int ising_create_in(int32_t L, uint64_t seed, int32_t init, void* dev_words, size_t bytes, void* stream,
                     ising_lattice** out);
 
+/* Re-initialise the lattice in place (cold or hot start with `seed`, as
+   ising_create) and set the sweep count to 0; enqueued on the handle's
+   stream, no allocation.  The seed of later sweeps becomes `seed`. */
+int ising_reset(ising_lattice* h, uint64_t seed, int32_t init);
+
 /* Release the handle (and the device memory the library allocated).
    Waits for the handle's stream first.  NULL is accepted. */
 int ising_destroy(ising_lattice* h);

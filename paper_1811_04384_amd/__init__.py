@@ -107,6 +107,10 @@ def ising_create_in(L, seed, init, dev_words, nbytes, stream=None):
     return h
 
 
+def ising_reset(h, seed, init):
+    _check(_lib.load().ising_reset(h, int(seed), int(init)))
+
+
 def ising_destroy(h):
     _check(_lib.load().ising_destroy(h))
 
@@ -293,6 +297,12 @@ class Lattice:
         self.stream = stream
         self.words = torch.empty(nbytes // 8, dtype=torch.int64, device=device)
         self.handle = ising_create_in(self.L, self.seed, ISING_HOT if hot else ISING_COLD, self.words, nbytes, stream)
+
+    def reset(self, seed=None, hot=True):
+        if seed is not None:
+            self.seed = int(seed)
+        ising_reset(self.handle, self.seed, ISING_HOT if hot else ISING_COLD)
+        return self
 
     def sweep(self, T, n):
         ising_sweep(self.handle, T, n)

@@ -36,6 +36,7 @@ SIGNATURES = {
     "ising_last_error": (c_char_p, []),
     "ising_create": (c_int, [c_i32, c_u64, c_i32, c_vp, P(c_vp)]),
     "ising_create_in": (c_int, [c_i32, c_u64, c_i32, c_vp, c_sz, c_vp, P(c_vp)]),
+    "ising_reset": (c_int, [c_vp, c_u64, c_i32]),
     "ising_destroy": (c_int, [c_vp]),
     "ising_sweep": (c_int, [c_vp, c_dbl, c_i64]),
     "ising_sweep_measure": (c_int, [c_vp, c_dbl, c_i64, c_i32, c_vp, c_vp]),

@@ -156,8 +156,8 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // `ld(I, J)` / `st(I, J, v)` access the word lattice (global memory or LDS).
 // J0 = base + parity; words with J >= L do not exist (ragged last segment).
 // The draws of position 20 come from block 5 keyed by word column
-// 8*(J div 8) + (J mod 2) and output (J div 2) mod 4; when WPT == 4 and the
-// segment is 8-aligned one block serves all four words.
+// 8*(J div 8) + (J mod 2) and output (J div 2) mod 4; one block per thread
+// serves all of its words.
 template <int WPT, bool MEASURE, class Load, class Store>
 __device__ __forceinline__ void update_segment(const Load& ld, const Store& st, int I, int J0, const SweepArgs& a,
                                                uint32_t& anti, uint32_t& ups) {
@@ -204,25 +204,20 @@ __device__ __forceinline__ void update_segment(const Load& ld, const Store& st, 
             }
         }
     }
-    // block 5: position 20 (field 0)
+    // block 5: position 20 (field 0).  The words J0 + 2k of one thread lie in
+    // one aligned group of eight columns (2 WPT divides 8), so one block keyed
+    // by that group's same-colour base column serves all of them, word k
+    // taking output (J0 div 2 + k) mod 4.
     if (n_live == 21) {
-        if (WPT == 4) {
-            const uint32_t col = (uint32_t)(J0 & ~7) | (uint32_t)(J0 & 1);
-            const U4 r = philox_lane_c1(a.t_lo, row_base + col, a.t_hi, 5u | (1u << 3), a.k0, a.k1);
-            const int q0 = (J0 >> 1) & 3;  // 0 for an 8-aligned segment
-            const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+        const uint32_t col = ((uint32_t)J0 & ~7u) | ((uint32_t)J0 & 1u);
+        const U4 r = philox_lane_c1(a.t_lo, row_base + col, a.t_hi, 5u | (1u << 3), a.k0, a.k1);
+        const uint32_t q0 = ((uint32_t)J0 >> 1) & 3u;
 #pragma unroll
-            for (int k = 0; k < WPT; ++k) codes[k].lo |= accept_code(u[(q0 + k) & 3], a.t4, a.t8);
-        } else {
-#pragma unroll
-            for (int k = 0; k < WPT; ++k) {
-                const uint32_t J = (uint32_t)min(J0 + 2 * k, L - 1);
-                const uint32_t col = (J & ~7u) | (J & 1u);
-                const U4 r = philox_lane_c1(a.t_lo, row_base + col, a.t_hi, 5u | (1u << 3), a.k0, a.k1);
-                const uint32_t q = (J >> 1) & 3u;
-                const uint32_t u = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
-                codes[k].lo |= accept_code(u, a.t4, a.t8);
-            }
+        for (int k = 0; k < WPT; ++k) {
+            const uint32_t q = (q0 + (uint32_t)k) & 3u;
+            const uint32_t u = WPT == 4 ? (k == 0 ? r.x : k == 1 ? r.y : k == 2 ? r.z : r.w)
+                                        : (q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w);
+            codes[k].lo |= accept_code(u, a.t4, a.t8);
         }
     }
 

@@ -132,6 +132,15 @@ int ising_create_in(int32_t L, uint64_t seed, int32_t init, void* dev_words, siz
     return create_impl(L, seed, init, dev_words, bytes, stream, out);
 }
 
+int ising_reset(ising_lattice* h, uint64_t seed, int32_t init) {
+    if (!h) return fail(ISING_EINVAL, "ising_reset: null handle");
+    if (init != ISING_COLD && init != ISING_HOT) return fail(ISING_EINVAL, "ising_reset: init must be 0 or 1");
+    h->seed = seed;
+    h->t = 0;
+    ISING_HIP(launch_init(h->W, h->g, seed, init, h->stream));
+    return ISING_OK;
+}
+
 int ising_destroy(ising_lattice* h) {
     if (!h) return ISING_OK;
     hipError_t e = hipStreamSynchronize(h->stream);
