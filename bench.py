@@ -123,16 +123,30 @@ def ising_words_main():
     return n * L_MAIN
 
 
-def load_traffic():
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("ising_device.hpp", "ising_kernels.hip", "ising_common.hpp"):
+        with open(os.path.join(ROOT, "paper_1811_04384_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(plan):
     """HBM bytes per half-sweep launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration),
-    or None if the summary is missing."""
+    summary (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by what the same
+    counters read for a copy of known size).  None if the summary is
+    missing, was taken on different kernel sources or another plan."""
     path = os.path.join(ROOT, "profiles", "halfsweep_L32768_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
-        return {"bytes_per_launch": d["bytes_per_launch"], "source": "profiles/halfsweep_L32768_traffic.json",
-                "algorithmic_bytes_per_launch": d.get("algorithmic_bytes_per_launch")}
+        if d.get("kernel_source_sha256_16") != kernel_source_hash():
+            return None
+        if f"<{plan['words_per_thread']}," not in d["kernel"]:
+            return None
+        return d["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
 
@@ -345,7 +359,7 @@ def main():
     log(f"headline: L={L_MAIN} x T={TEMPS_MAIN} x {args.sweeps} sweeps, warmup {args.warmup}, steps {args.steps}")
     main_res = run_main(ising, args.steps, args.warmup, args.sweeps)
     log(f"headline: {main_res['value']:.1f} attempts/ns, {main_res['ms_per_step']:.1f} ms/step")
-    traffic = load_traffic()
+    traffic = load_traffic(main_res["plan"])
 
     secondary = {}
     wanted = [] if args.secondary == "none" else args.secondary.split(",")

@@ -94,36 +94,69 @@ __device__ __forceinline__ uint64_t down_word(const Load& ld, int I, int J, int 
     return d;
 }
 
-// Acceptance bits of one position: 1 if u < t4, 3 if u < t8 (t8 <= t4, so
-// u < t8 implies u < t4), else 0.  Field bit 0 says "accepted if dE = +4",
-// bit 1 says "accepted if dE = +8".
+// Acceptance code of one position: the number of thresholds above its
+// uniform, (u < t4) + (u < t8) in {0, 1, 2} (t8 <= t4, so u < t8 implies
+// u < t4).  A move with dE = +4 is accepted iff the code is >= 1, one with
+// dE = +8 iff it is 2 (Section 2, step 3 with the energies of Table 1).
 __device__ __forceinline__ uint32_t accept_code(uint32_t u, uint32_t t4, uint32_t t8) {
-    uint32_t x = (u < t4) ? 1u : 0u;
-    return (u < t8) ? 3u : x;
+    const uint32_t x = (u < t4) ? 1u : 0u;
+    return (u < t8) ? 2u : x;
 }
 
 // The 21 per-position acceptance codes of one word packed in word layout
-// (code of position p in field 20 - p), built from the six Philox blocks:
-// block g < 5 serves positions 4g..4g+3, block 5 serves position 20 (taken
-// from output q5 of a block shared by four same-colour words).
+// (code of position p in field 20 - p).  They are appended in position order
+// with acc = (acc << 3) | code, so every code is a small inline constant.
 struct Codes {
-    uint32_t hi;  // fields 11..20 -> word bits 33..62 (stored as bits 1..30)
-    uint32_t mid; // field 10     -> word bits 30..32
-    uint32_t lo;  // fields 0..9  -> word bits 0..29
+    uint32_t hi;  // positions 0..9  = fields 20..11 -> word bits 33..62 (bits 0..29 here)
+    uint32_t mid; // position 10     = field 10     -> word bits 30..31
+    uint32_t lo;  // positions 11..20 = fields 9..0  -> word bits 0..29
 };
+
+__device__ __forceinline__ void append_code(Codes& c, int p, uint32_t code) {
+    if (p < 10) c.hi = (c.hi << 3) | code;
+    else if (p == 10) c.mid = code;
+    else c.lo = (c.lo << 3) | code;
+}
+
+// acc = (acc << 3) | accept_code(u), as five VALU instructions: two compares
+// into lane masks, two selects of inline constants, one shift-or.  Written
+// out because the compiler otherwise folds the shift into selects of
+// pre-shifted literals, which need extra moves on this target.  The s_nop
+// gives the lane masks the wait states a VALU read of a VALU-written SGPR
+// needs.  ALU instructions only (no memory access).
+__device__ __forceinline__ uint32_t append_accept(uint32_t acc, uint32_t u, uint32_t t4, uint32_t t8) {
+    uint32_t x;
+    uint64_t m4, m8;
+    asm("v_cmp_gt_u32_e64 %[m4], %[t4], %[u]\n\t"
+        "v_cmp_gt_u32_e64 %[m8], %[t8], %[u]\n\t"
+        "s_nop 1\n\t"
+        "v_cndmask_b32_e64 %[x], 0, 1, %[m4]\n\t"
+        "v_cndmask_b32_e64 %[x], %[x], 2, %[m8]\n\t"
+        "v_lshl_or_b32 %[acc], %[acc], 3, %[x]"
+        : [acc] "+v"(acc), [x] "=&v"(x), [m4] "=&s"(m4), [m8] "=&s"(m8)
+        : [u] "v"(u), [t4] "s"(t4), [t8] "s"(t8));
+    return acc;
+}
+
+__device__ __forceinline__ void append_draw(Codes& c, int p, uint32_t u, uint32_t t4, uint32_t t8) {
+    if (p < 10) c.hi = append_accept(c.hi, u, t4, t8);
+    else if (p == 10) c.mid = accept_code(u, t4, t8);
+    else c.lo = append_accept(c.lo, u, t4, t8);
+}
 
 // Flip mask of a word.  a..d = w XOR neighbour (only bit 3k meaningful);
 // n = number of set inputs per field.  A spin flips iff n >= 2 (dE <= 0), or
-// n = 1 and u < t4 (dE = +4), or n = 0 and u < t8 (dE = +8) (Table 1 and the
-// Metropolis rule of Section 2).  With the code bits c0 (u < t4) and
-// c1 (u < t8, which implies c0): flip = c1 | (c0 & n>=1) | n>=2.
+// n = 1 and code >= 1 (dE = +4), or n = 0 and code = 2 (dE = +8) (Table 1
+// and the Metropolis rule of Section 2).  With code bits c0 = [code = 1] and
+// c1 = [code = 2]: flip = c1 | ((c0 | c1) & n>=1) | n>=2.
 __device__ __forceinline__ uint64_t flip_mask(uint64_t w, uint64_t up, uint64_t dn, uint64_t lf, uint64_t rt,
                                               uint64_t codes, uint64_t live) {
     const uint64_t a = w ^ up, b = w ^ dn, c = w ^ lf, d = w ^ rt;
     const uint64_t ab_or = a | b, cd_or = c | d;
     const uint64_t ge1 = ab_or | cd_or;
     const uint64_t ge2 = (a & b) | (c & d) | (ab_or & cd_or);
-    return ((codes >> 1) | (codes & ge1) | ge2) & live;
+    const uint64_t c1 = codes >> 1;
+    return (c1 | ((codes | c1) & ge1) | ge2) & live;
 }
 
 __device__ __forceinline__ uint64_t assemble_codes(const Codes& c) {
@@ -156,78 +189,66 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // `ld(I, J)` / `st(I, J, v)` access the word lattice (global memory or LDS).
 // J0 = base + parity; words with J >= L do not exist (ragged last segment).
 // The draws of position 20 come from block 5 keyed by word column
-// 8*(J div 8) + (J mod 2) and output (J div 2) mod 4; one block per thread
-// serves all of its words.
+// 8*(J div 8) + (J mod 2) and output (J div 2) mod 4.  The words J0 + 2k of
+// one thread lie in one aligned group of eight columns (2 WPT divides 8), so
+// one block, drawn first, serves all of them; the words are then updated one
+// after another, each with its five independent blocks g = 0..4, which keeps
+// few registers live.
 template <int WPT, bool MEASURE, class Load, class Store>
 __device__ __forceinline__ void update_segment(const Load& ld, const Store& st, int I, int J0, const SweepArgs& a,
                                                uint32_t& anti, uint32_t& ups) {
     const int L = a.L, N = a.N;
-    const uint64_t live = live_mask(I, L, N);
     const int n_live = min(21, (L - 1 - I) / N + 1);
+    const uint64_t live = kSpinBits & (~0ull << (3 * (21 - n_live)));
     const uint32_t row_base = (uint32_t)I * (uint32_t)L;
 
-    uint64_t w[WPT], up[WPT], dn[WPT], lf[WPT], rt[WPT];
-    bool ok[WPT];
-#pragma unroll
-    for (int k = 0; k < WPT; ++k) {
-        const int J = J0 + 2 * k;
-        ok[k] = J < L;
-        const int Jc = ok[k] ? J : J0;  // keep loads in bounds for the ragged tail
-        w[k] = ld(I, Jc);
-        lf[k] = ld(I, Jc == 0 ? L - 1 : Jc - 1);
-        rt[k] = ld(I, Jc == L - 1 ? 0 : Jc + 1);
-        up[k] = up_word(ld, I, Jc, N, a.istar, a.sh_star);
-        dn[k] = down_word(ld, I, Jc, N, a.istar, a.sh_star);
-    }
-
-    Codes codes[WPT];
-#pragma unroll
-    for (int k = 0; k < WPT; ++k) codes[k] = {0u, 0u, 0u};
-
-    // blocks g = 0..4: positions 4g..4g+3 of each word
-#pragma unroll
-    for (int g = 0; g < 5; ++g) {
-        if (4 * g >= n_live) break;  // every position of the block is a dead slot
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) {
-            const uint32_t col = (uint32_t)min(J0 + 2 * k, L - 1);
-            const U4 r = philox_lane_c1(a.t_lo, row_base + col, a.t_hi, (uint32_t)g | (1u << 3), a.k0, a.k1);
-            const uint32_t u[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int p = 4 * g + j;  // position; field 20 - p
-                const int field = 20 - p;
-                const uint32_t cde = accept_code(u[j], a.t4, a.t8);
-                if (field >= 11) codes[k].hi |= cde << (3 * field - 33);
-                else if (field == 10) codes[k].mid = cde;
-                else codes[k].lo |= cde << (3 * field);
-            }
-        }
-    }
-    // block 5: position 20 (field 0).  The words J0 + 2k of one thread lie in
-    // one aligned group of eight columns (2 WPT divides 8), so one block keyed
-    // by that group's same-colour base column serves all of them, word k
-    // taking output (J0 div 2 + k) mod 4.
+    // position-20 draws of the segment's words, word k's draw in u5[k]
+    uint32_t u5[4] = {0u, 0u, 0u, 0u};
     if (n_live == 21) {
         const uint32_t col = ((uint32_t)J0 & ~7u) | ((uint32_t)J0 & 1u);
         const U4 r = philox_lane_c1(a.t_lo, row_base + col, a.t_hi, 5u | (1u << 3), a.k0, a.k1);
-        const uint32_t q0 = ((uint32_t)J0 >> 1) & 3u;
+        if (WPT == 4) {  // segments are 8-aligned: output k belongs to word k
+            u5[0] = r.x;
+            u5[1] = r.y;
+            u5[2] = r.z;
+            u5[3] = r.w;
+        } else {
+            const uint32_t q0 = ((uint32_t)J0 >> 1) & 3u;  // first word's output
 #pragma unroll
-        for (int k = 0; k < WPT; ++k) {
-            const uint32_t q = (q0 + (uint32_t)k) & 3u;
-            const uint32_t u = WPT == 4 ? (k == 0 ? r.x : k == 1 ? r.y : k == 2 ? r.z : r.w)
-                                        : (q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w);
-            codes[k].lo |= accept_code(u, a.t4, a.t8);
+            for (int k = 0; k < WPT; ++k) {
+                const uint32_t q = (q0 + (uint32_t)k) & 3u;
+                u5[k] = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
+            }
         }
     }
 
 #pragma unroll
     for (int k = 0; k < WPT; ++k) {
-        if (!ok[k]) continue;
-        const uint64_t f = flip_mask(w[k], up[k], dn[k], lf[k], rt[k], assemble_codes(codes[k]), live);
-        const uint64_t nw = w[k] ^ f;
-        st(I, J0 + 2 * k, nw);
-        if (MEASURE) measure_word(nw, up[k], dn[k], lf[k], rt[k], live, anti, ups);
+        const int J = J0 + 2 * k;
+        if (J >= L) break;
+        const uint64_t w = ld(I, J);
+        const uint64_t lf = ld(I, J == 0 ? L - 1 : J - 1);
+        const uint64_t rt = ld(I, J == L - 1 ? 0 : J + 1);
+        const uint64_t up = up_word(ld, I, J, N, a.istar, a.sh_star);
+        const uint64_t dn = down_word(ld, I, J, N, a.istar, a.sh_star);
+
+        Codes codes = {0u, 0u, 0u};
+#pragma unroll
+        for (int g = 0; g < 5; ++g) {
+            U4 r = {0u, 0u, 0u, 0u};  // positions past the last live one are dead slots
+            if (4 * g < n_live)
+                r = philox_lane_c1(a.t_lo, row_base + (uint32_t)J, a.t_hi, (uint32_t)g | (1u << 3), a.k0, a.k1);
+            append_draw(codes, 4 * g + 0, r.x, a.t4, a.t8);
+            append_draw(codes, 4 * g + 1, r.y, a.t4, a.t8);
+            append_draw(codes, 4 * g + 2, r.z, a.t4, a.t8);
+            append_draw(codes, 4 * g + 3, r.w, a.t4, a.t8);
+        }
+        append_draw(codes, 20, u5[k], a.t4, a.t8);  // dead slot when n_live < 21
+
+        const uint64_t f = flip_mask(w, up, dn, lf, rt, assemble_codes(codes), live);
+        const uint64_t nw = w ^ f;
+        st(I, J, nw);
+        if (MEASURE) measure_word(nw, up, dn, lf, rt, live, anti, ups);
     }
 }
 

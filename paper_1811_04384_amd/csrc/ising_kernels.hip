@@ -60,7 +60,22 @@ __global__ void __launch_bounds__(256) k_init(uint64_t* __restrict__ W, Geometry
 // Half-sweep of one lattice held in global memory.  One thread per row
 // segment; a segment holds WPT words of the colour being updated.
 // ---------------------------------------------------------------------------
-template <int WPT, bool MEASURE>
+// Word accessors.  With OFF32 (lattice smaller than 4 GiB) the byte offset
+// is a 32-bit value added to the wave-uniform base, which the global loads
+// take directly (scalar base + 32-bit vector offset).
+template <bool OFF32>
+struct WordPtr {
+    uint64_t* __restrict__ W;
+    uint32_t L;
+    __device__ __forceinline__ uint64_t* at(int i, int j) const {
+        if (OFF32)
+            return reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(W) +
+                                               (((uint32_t)i * L + (uint32_t)j) << 3));
+        return W + ((size_t)i * L + (size_t)j);
+    }
+};
+
+template <int WPT, bool MEASURE, bool OFF32>
 __global__ void __launch_bounds__(kTiledMaxBlock)
     k_halfsweep_single(uint64_t* __restrict__ W, SweepArgs a, int32_t segs, uint32_t units, int colour,
                        Partial* __restrict__ partials) {
@@ -70,9 +85,9 @@ __global__ void __launch_bounds__(kTiledMaxBlock)
         const int I = (int)(unit / (uint32_t)segs);
         const int seg = (int)(unit - (uint32_t)I * (uint32_t)segs);
         const int J0 = seg * 2 * WPT + ((I + colour) & 1);
-        const size_t L = (size_t)a.L;
-        auto ld = [&](int i, int j) { return W[(size_t)i * L + j]; };
-        auto st = [&](int i, int j, uint64_t v) { W[(size_t)i * L + j] = v; };
+        const WordPtr<OFF32> p{W, (uint32_t)a.L};
+        auto ld = [&](int i, int j) { return *p.at(i, j); };
+        auto st = [&](int i, int j, uint64_t v) { *p.at(i, j) = v; };
         update_segment<WPT, MEASURE>(ld, st, I, J0, a, anti, ups);
     }
     if (MEASURE) {
@@ -413,9 +428,18 @@ hipError_t launch_halfsweep_single(int wpt, int block, uint64_t* W, const SweepA
     const dim3 grid(grid_for(units, block)), blk(block);
     if (n_waves) *n_waves = (int64_t)grid.x * block / 64;
     const bool m = partials != nullptr;
-#define ISING_LAUNCH_HS(WPT_)                                                                                  \
-    if (m) hipLaunchKernelGGL((k_halfsweep_single<WPT_, true>), grid, blk, 0, s, W, a, segs, units, colour, partials); \
-    else hipLaunchKernelGGL((k_halfsweep_single<WPT_, false>), grid, blk, 0, s, W, a, segs, units, colour, partials);
+    const bool off32 = (uint64_t)g.N * (uint64_t)g.L * 8u < (1ull << 32);
+#define ISING_LAUNCH_HS2(WPT_, O_)                                                                                \
+    if (m) hipLaunchKernelGGL((k_halfsweep_single<WPT_, true, O_>), grid, blk, 0, s, W, a, segs, units, colour,   \
+                              partials);                                                                          \
+    else hipLaunchKernelGGL((k_halfsweep_single<WPT_, false, O_>), grid, blk, 0, s, W, a, segs, units, colour,    \
+                            partials);
+#define ISING_LAUNCH_HS(WPT_)            \
+    if (off32) {                         \
+        ISING_LAUNCH_HS2(WPT_, true)     \
+    } else {                             \
+        ISING_LAUNCH_HS2(WPT_, false)    \
+    }
     switch (wpt) {
         case 1: ISING_LAUNCH_HS(1) break;
         case 2: ISING_LAUNCH_HS(2) break;
@@ -423,6 +447,7 @@ hipError_t launch_halfsweep_single(int wpt, int block, uint64_t* W, const SweepA
         default: return hipErrorInvalidValue;
     }
 #undef ISING_LAUNCH_HS
+#undef ISING_LAUNCH_HS2
     return hipGetLastError();
 }
 

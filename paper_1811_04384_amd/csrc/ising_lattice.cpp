@@ -110,8 +110,9 @@ static int create_impl(int32_t L, uint64_t seed, int32_t init, void* dev_words, 
         release(h);
         return fail(ISING_ENOMEM, "ising_create: scratch allocation failed: %s", hipGetErrorString(e));
     }
-    // default plan: four words per thread unless that leaves the chip idle
-    h->wpt = units_per_colour(h->g, 4) >= 64 * 1024 ? 4 : (units_per_colour(h->g, 2) >= 64 * 1024 ? 2 : 1);
+    // default plan: two words per thread (fastest measured on gfx950 for
+    // large lattices) unless that leaves the chip short of wavefronts
+    h->wpt = units_per_colour(h->g, 2) >= 64 * 1024 ? 2 : 1;
     h->block = 256;
     e = launch_init(h->W, h->g, seed, init, h->stream);
     if (e != hipSuccess) {
