@@ -199,6 +199,31 @@ def run_plain4096(ising, sweeps=10000, every=10):
             "mean_e_per_spin": round(e, 6)}
 
 
+def run_graph4096(ising, sweeps=10000, every=10):
+    """The same L=4096 workload through the batch engine with one lattice:
+    still one lattice per launch, but the launches replayed from hipGraph
+    chunks instead of issued one by one from the host."""
+    import torch
+
+    b = ising.Batch([4096], [7], hot=True)
+    b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=2, tiled_block=256, sweeps_per_graph=100)
+    b.sweep([2.269], 100, every=every)
+    b.close()
+    b = ising.Batch([4096], [7], hot=True)
+    b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=2, tiled_block=256, sweeps_per_graph=100)
+    b.sweep([2.269], 100, every=every)  # capture the chunk graph before timing
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    b.sweep([2.269], sweeps, every=every)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    b.close()
+    return {"workload": "L=4096 single, hot seed 7, T=2.269, 10000 sweeps, E/M every 10, graph-replayed launches",
+            "value": round(4096 ** 2 * sweeps / (ms * 1e6), 2), "unit": UNIT, "ms": round(ms, 2)}
+
+
 def batched_config():
     Ls = [(256, 512, 1024, 2048)[i % 4] for i in range(2048)]
     Ts = [1.5 + 2.0 * ((i // 4) % 32) / 31 for i in range(2048)]
@@ -324,7 +349,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sweeps", type=int, default=SWEEPS_MAIN, help="sweeps per temperature (headline: 2000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--secondary", default="plain4096,batched,scan64,serving",
+    ap.add_argument("--secondary", default="plain4096,graph4096,batched,scan64,serving",
                     help="comma list of secondary workloads, or 'none'")
     ap.add_argument("--serving-rate", type=float, default=25.0)
     ap.add_argument("--serving-duration", type=float, default=10.0)
@@ -367,6 +392,8 @@ def main():
         log(f"secondary: {name}")
         if name == "plain4096":
             secondary[name] = run_plain4096(ising)
+        elif name == "graph4096":
+            secondary[name] = run_graph4096(ising)
         elif name == "batched":
             secondary[name] = run_batched(ising)
         elif name == "scan64":

@@ -60,6 +60,7 @@ struct ising_batch {
     int32_t* d_ids_glb = nullptr;
     int32_t n_glb = 0;
     int32_t n_tiled = 0;
+    bool off32 = true;  // every tiled lattice < 4 GiB
     std::map<std::pair<int32_t, int32_t>, hipGraphExec_t> graphs;  // (sweeps, every) -> executable
 };
 
@@ -160,6 +161,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     std::vector<int32_t> ids_lds, ids_glb;
     std::vector<WaveItem> waves;
     size_t max_lds = 0;
+    b->off32 = true;
     for (int32_t i = 0; i < b->n; ++i) {
         const Geometry& g = b->geo[i];
         if (g.L <= p.resident_max_L) {
@@ -175,6 +177,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
         }
         const int64_t u = units_per_colour(g, p.words_per_thread);
         b->units[i] = u;
+        b->off32 = b->off32 && fits_off32(g);
         b->part_begin[i] = (int32_t)waves.size();
         for (int64_t u0 = 0; u0 < u; u0 += 64) waves.push_back({i, (int32_t)u0});
         b->part_count[i] = (int32_t)waves.size() - b->part_begin[i];
@@ -221,9 +224,9 @@ int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipS
         for (int32_t s = 0; s < k; ++s) {
             const bool meas = every > 0 && (s + 1) % every == 0;
             ISING_HIP(launch_halfsweep_multi(p.words_per_thread, p.tiled_block, b->d_desc, b->d_state, b->d_waves,
-                                             b->n_waves, 0, (uint32_t)s, nullptr, s0));
+                                             b->n_waves, 0, (uint32_t)s, nullptr, b->off32, s0));
             ISING_HIP(launch_halfsweep_multi(p.words_per_thread, p.tiled_block, b->d_desc, b->d_state, b->d_waves,
-                                             b->n_waves, 1, (uint32_t)s, meas ? b->d_partials : nullptr, s0));
+                                             b->n_waves, 1, (uint32_t)s, meas ? b->d_partials : nullptr, b->off32, s0));
             if (meas) ISING_HIP(launch_finalize_multi(b->d_desc, b->d_state, b->n, b->d_partials, (uint32_t)s, s0));
         }
     }
@@ -427,26 +430,32 @@ void cache_store(const char* path, const std::string& key, const ising_batch_pla
     f << "}\n";
 }
 
-// Time `sweeps` sweeps of a scratch batch under plan p; ms per sweep.
+// Time `sweeps` sweeps of a scratch batch under plan p: best of two runs
+// after a warm-up that captures the chunk graphs; ms per sweep.
 int time_plan(ising_batch* s, const ising_batch_plan& p, const double* T, int32_t sweeps, double* ms_per_sweep) {
     int rc = apply_plan(s, p);
     if (rc != ISING_OK) return rc;
-    rc = sweep_impl(s, T, std::min(sweeps, p.sweeps_per_graph), 0, nullptr, nullptr);  // capture + warm-up
+    rc = sweep_impl(s, T, sweeps, 0, nullptr, nullptr);  // captures every chunk length used below
     if (rc != ISING_OK) return rc;
     hipEvent_t e0, e1;
     ISING_HIP(hipEventCreate(&e0));
     ISING_HIP(hipEventCreate(&e1));
-    hipError_t e = hipEventRecord(e0, s->stream);
-    if (e == hipSuccess) rc = sweep_impl(s, T, sweeps, 0, nullptr, nullptr);
-    if (e == hipSuccess && rc == ISING_OK) e = hipEventRecord(e1, s->stream);
-    if (e == hipSuccess && rc == ISING_OK) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess && rc == ISING_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    double best = 1e300;
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 2 && rc == ISING_OK && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, s->stream);
+        if (e == hipSuccess) rc = sweep_impl(s, T, sweeps, 0, nullptr, nullptr);
+        if (e == hipSuccess && rc == ISING_OK) e = hipEventRecord(e1, s->stream);
+        if (e == hipSuccess && rc == ISING_OK) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess && rc == ISING_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && rc == ISING_OK) best = std::min(best, (double)ms / sweeps);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != ISING_OK) return rc;
     if (e != hipSuccess) return hip_fail(e, "autotune timing");
-    *ms_per_sweep = ms / sweeps;
+    *ms_per_sweep = best;
     return ISING_OK;
 }
 
@@ -475,7 +484,7 @@ int ising_batch_sweep(ising_batch* b, const double* T, int64_t n_sweeps, int32_t
 int ising_batch_results(ising_batch* b, int64_t* E, int64_t* M, int64_t* sum_E, int64_t* sum_absM,
                         int64_t* n_samples) {
     if (!b) return fail(ISING_EINVAL, "ising_batch_results: null handle");
-    if (E || M) ISING_HIP(launch_observe_multi(b->d_desc, b->d_state, nullptr, b->n, b->stream));
+    if (E || M) ISING_HIP(launch_observe_multi(b->d_desc, b->d_state, nullptr, b->n, nullptr, b->stream));
     std::vector<LatticeState> st(b->n);
     ISING_HIP(hipMemcpyAsync(st.data(), b->d_state, sizeof(LatticeState) * b->n, hipMemcpyDeviceToHost, b->stream));
     ISING_HIP(hipStreamSynchronize(b->stream));
@@ -558,8 +567,8 @@ int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path
     ising_batch_plan p0 = b->plan;
     int rc = create_impl(b->n, L.data(), seeds.data(), init.data(), b->stream, &s, &p0);
     if (rc != ISING_OK) return rc;
-    // about 20 ms of work per timing at ~1 attempt/ps
-    const int32_t sweeps = (int32_t)std::max(4.0, std::min(2000.0, 2e10 / std::max(total_spins, 1.0)));
+    // about 50 ms of work per timing at ~2 attempts/ps, at least 20 sweeps
+    const int32_t sweeps = (int32_t)std::max(20.0, std::min(2000.0, 1e11 / std::max(total_spins, 1.0)));
     double best_ms = 1e300;
     best = p0;
     auto consider = [&](const ising_batch_plan& p) -> int {
@@ -580,7 +589,7 @@ int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path
             p.resident_max_L = 0;
             p.words_per_thread = wpt;
             p.tiled_block = blk;
-            p.sweeps_per_graph = std::min(sweeps, 50);
+            p.sweeps_per_graph = std::min(sweeps, 20);
             rc = consider(p);
         }
     // 2) which sizes go resident, and the resident workgroup size
@@ -595,7 +604,7 @@ int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path
         }
     // 3) sweeps per graph
     const ising_batch_plan shape_best = best;
-    for (int k : {10, 25, 100, 250}) {
+    for (int k : {10, 50, 100, 250}) {
         if (rc != ISING_OK) break;
         ising_batch_plan p = shape_best;
         p.sweeps_per_graph = std::min(k, sweeps);

@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(kTiledMaxBlock)
 // wavefront belongs to one lattice, so the lattice's parameters (key, sweep
 // index, thresholds) are wave-uniform and live in scalar registers.
 // ---------------------------------------------------------------------------
-template <int WPT, bool MEASURE>
+template <int WPT, bool MEASURE, bool OFF32>
 __global__ void __launch_bounds__(kTiledMaxBlock)
     k_halfsweep_multi(const LatticeDesc* __restrict__ descs, const LatticeState* __restrict__ states,
                       const WaveItem* __restrict__ waves, uint32_t n_waves, int colour, uint32_t sweep_off,
@@ -117,7 +117,6 @@ __global__ void __launch_bounds__(kTiledMaxBlock)
     }
     const uint64_t t = states[item.lattice].t + sweep_off;
     const SweepArgs a = {d.L, d.N, d.istar, d.sh_star, (uint32_t)t, (uint32_t)(t >> 32), d.k0, d.k1, d.t4, d.t8};
-    uint64_t* __restrict__ W = d.W;
     const uint32_t unit = (uint32_t)item.unit0 + (uint32_t)lane_id();
     uint32_t anti = 0, ups = 0;
     if (unit < (uint32_t)d.units) {
@@ -125,9 +124,9 @@ __global__ void __launch_bounds__(kTiledMaxBlock)
         const int I = (int)(unit / (uint32_t)segs);
         const int seg = (int)(unit - (uint32_t)I * (uint32_t)segs);
         const int J0 = seg * 2 * WPT + ((I + colour) & 1);
-        const size_t L = (size_t)a.L;
-        auto ld = [&](int i, int j) { return W[(size_t)i * L + j]; };
-        auto st = [&](int i, int j, uint64_t v) { W[(size_t)i * L + j] = v; };
+        const WordPtr<OFF32> p{d.W, (uint32_t)a.L};
+        auto ld = [&](int i, int j) { return *p.at(i, j); };
+        auto st = [&](int i, int j, uint64_t v) { *p.at(i, j) = v; };
         update_segment<WPT, MEASURE>(ld, st, I, J0, a, anti, ups);
     }
     if (MEASURE) {
@@ -166,14 +165,40 @@ __device__ __forceinline__ void energy_magnetisation(uint64_t anti, uint64_t ups
     M = 2 * (int64_t)ups - n;
 }
 
-__global__ void __launch_bounds__(1024) k_finalize_single(const Partial* __restrict__ partials, int64_t n_partials,
-                                                          int32_t L, int64_t* series_E, int64_t* series_M,
-                                                          int64_t idx, int64_t* out_EM) {
+// Grid reduction of one lattice's wavefront partials: every workgroup sums a
+// slice into block_sums[blockIdx.x]; the last workgroup to finish (ticket
+// counter at device scope) adds the slices, turns them into E, M and resets
+// the counter for the next call.
+constexpr int kFinalizeBlocks = 256;
+
+__global__ void __launch_bounds__(256) k_finalize_single(const Partial* __restrict__ partials, int64_t n_partials,
+                                                         int32_t L, int64_t* series_E, int64_t* series_M,
+                                                         int64_t idx, int64_t* out_EM,
+                                                         unsigned long long* __restrict__ block_sums,
+                                                         unsigned int* __restrict__ ticket) {
     __shared__ uint64_t red[32];
+    __shared__ bool last;
     uint64_t anti = 0, ups = 0;
-    for (int64_t i = threadIdx.x; i < n_partials; i += blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_partials;
+         i += (int64_t)gridDim.x * blockDim.x) {
         anti += partials[i].anti;
         ups += partials[i].ups;
+    }
+    block_sum2(anti, ups, red);
+    if (threadIdx.x == 0) {
+        block_sums[2 * blockIdx.x] = anti;
+        block_sums[2 * blockIdx.x + 1] = ups;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    anti = 0;
+    ups = 0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+        anti += __atomic_load_n(&block_sums[2 * i], __ATOMIC_RELAXED);
+        ups += __atomic_load_n(&block_sums[2 * i + 1], __ATOMIC_RELAXED);
     }
     block_sum2(anti, ups, red);
     if (threadIdx.x == 0) {
@@ -185,6 +210,7 @@ __global__ void __launch_bounds__(1024) k_finalize_single(const Partial* __restr
             out_EM[0] = E;
             out_EM[1] = M;
         }
+        *ticket = 0u;
     }
 }
 
@@ -325,7 +351,7 @@ __global__ void __launch_bounds__(kResidentMaxBlock)
 // antiparallel right and down bonds (Section 5.3) and up spins.
 __global__ void __launch_bounds__(256) k_observe_multi(const LatticeDesc* __restrict__ descs,
                                                        LatticeState* __restrict__ states,
-                                                       const int32_t* __restrict__ ids) {
+                                                       const int32_t* __restrict__ ids, int64_t* __restrict__ out_EM) {
     __shared__ uint64_t red[32];
     const int32_t lat = ids ? ids[blockIdx.x] : (int32_t)blockIdx.x;
     const LatticeDesc& d = descs[lat];
@@ -350,6 +376,10 @@ __global__ void __launch_bounds__(256) k_observe_multi(const LatticeDesc* __rest
         energy_magnetisation(anti, ups, L, E, M);
         states[lat].last_E = E;
         states[lat].last_M = M;
+        if (out_EM) {
+            out_EM[2 * blockIdx.x] = E;
+            out_EM[2 * blockIdx.x + 1] = M;
+        }
     }
 }
 
@@ -451,10 +481,16 @@ hipError_t launch_halfsweep_single(int wpt, int block, uint64_t* W, const SweepA
     return hipGetLastError();
 }
 
+size_t finalize_scratch_bytes() { return 2 * kFinalizeBlocks * sizeof(unsigned long long) + 256; }
+
 hipError_t launch_finalize_single(const Partial* partials, int64_t n_partials, int32_t L, int64_t* series_E,
-                                  int64_t* series_M, int64_t idx, int64_t* out_EM, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_single, dim3(1), dim3(1024), 0, s, partials, n_partials, L, series_E, series_M,
-                       idx, out_EM);
+                                  int64_t* series_M, int64_t idx, int64_t* out_EM, void* scratch, hipStream_t s) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kFinalizeBlocks, (n_partials + 2047) / 2048));
+    unsigned long long* sums = reinterpret_cast<unsigned long long*>(scratch);
+    unsigned int* ticket = reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(scratch) +
+                                                           2 * kFinalizeBlocks * sizeof(unsigned long long));
+    hipLaunchKernelGGL(k_finalize_single, dim3(blocks), dim3(256), 0, s, partials, n_partials, L, series_E, series_M,
+                       idx, out_EM, sums, ticket);
     return hipGetLastError();
 }
 
@@ -483,16 +519,22 @@ hipError_t launch_pack(const uint8_t* in, const Geometry& g, uint64_t* W, hipStr
 
 hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, const LatticeState* states,
                                   const WaveItem* waves, int64_t n_waves, int colour, uint32_t sweep_off,
-                                  Partial* partials, hipStream_t s) {
+                                  Partial* partials, bool off32, hipStream_t s) {
     if (n_waves <= 0) return hipSuccess;
     const dim3 grid(grid_for((uint64_t)n_waves * 64, block)), blk(block);
     const bool m = partials != nullptr;
     const uint32_t nw = (uint32_t)n_waves;
-#define ISING_LAUNCH_HM(WPT_)                                                                                       \
-    if (m) hipLaunchKernelGGL((k_halfsweep_multi<WPT_, true>), grid, blk, 0, s, descs, states, waves, nw, colour,  \
-                              sweep_off, partials);                                                                 \
-    else hipLaunchKernelGGL((k_halfsweep_multi<WPT_, false>), grid, blk, 0, s, descs, states, waves, nw, colour,   \
-                            sweep_off, partials);
+#define ISING_LAUNCH_HM2(WPT_, O_)                                                                                  \
+    if (m) hipLaunchKernelGGL((k_halfsweep_multi<WPT_, true, O_>), grid, blk, 0, s, descs, states, waves, nw,       \
+                              colour, sweep_off, partials);                                                         \
+    else hipLaunchKernelGGL((k_halfsweep_multi<WPT_, false, O_>), grid, blk, 0, s, descs, states, waves, nw,        \
+                            colour, sweep_off, partials);
+#define ISING_LAUNCH_HM(WPT_)           \
+    if (off32) {                        \
+        ISING_LAUNCH_HM2(WPT_, true)    \
+    } else {                            \
+        ISING_LAUNCH_HM2(WPT_, false)   \
+    }
     switch (wpt) {
         case 1: ISING_LAUNCH_HM(1) break;
         case 2: ISING_LAUNCH_HM(2) break;
@@ -500,6 +542,7 @@ hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, 
         default: return hipErrorInvalidValue;
     }
 #undef ISING_LAUNCH_HM
+#undef ISING_LAUNCH_HM2
     return hipGetLastError();
 }
 
@@ -529,9 +572,9 @@ hipError_t launch_begin_call(LatticeState* states, int32_t n_lat, hipStream_t s)
 }
 
 hipError_t launch_observe_multi(const LatticeDesc* descs, LatticeState* states, const int32_t* ids, int32_t n_lat,
-                                hipStream_t s) {
+                                int64_t* out_EM, hipStream_t s) {
     if (n_lat <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_observe_multi, dim3(n_lat), dim3(256), 0, s, descs, states, ids);
+    hipLaunchKernelGGL(k_observe_multi, dim3(n_lat), dim3(256), 0, s, descs, states, ids, out_EM);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct ising_lattice {
     Partial* partials = nullptr;  // per-wavefront bond/spin counts
     int64_t partial_cap = 0;
     int64_t* d_EM = nullptr;  // device scratch: E, M of ising_observables
+    void* d_fin = nullptr;    // device scratch of the partial-sum reduction
 };
 
 namespace ising {
@@ -68,6 +69,7 @@ static void release(ising_lattice* h) {
     if (h->owns_W && h->W) (void)hipFree(h->W);
     if (h->partials) (void)hipFree(h->partials);
     if (h->d_EM) (void)hipFree(h->d_EM);
+    if (h->d_fin) (void)hipFree(h->d_fin);
     delete h;
 }
 
@@ -106,6 +108,8 @@ static int create_impl(int32_t L, uint64_t seed, int32_t init, void* dev_words, 
     h->partial_cap = partials_needed(h->g);
     e = hipMalloc(&h->partials, (size_t)h->partial_cap * sizeof(Partial));
     if (e == hipSuccess) e = hipMalloc(&h->d_EM, 2 * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&h->d_fin, finalize_scratch_bytes());
+    if (e == hipSuccess) e = hipMemsetAsync(h->d_fin, 0, finalize_scratch_bytes(), h->stream);
     if (e != hipSuccess) {
         release(h);
         return fail(ISING_ENOMEM, "ising_create: scratch allocation failed: %s", hipGetErrorString(e));
@@ -178,7 +182,8 @@ static int enqueue_sweeps(const ising_lattice* h, uint64_t* W, uint64_t t0, doub
         int64_t nw = 0;
         ISING_HIP(launch_halfsweep_single(wpt, block, W, a, 1, meas ? h->partials : nullptr, &nw, h->stream));
         if (meas)
-            ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, dev_E, dev_M, k / every - 1, nullptr, h->stream));
+            ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, dev_E, dev_M, k / every - 1, nullptr, h->d_fin,
+                                             h->stream));
     }
     return ISING_OK;
 }
@@ -206,7 +211,7 @@ int ising_observables(ising_lattice* h, int64_t* E, int64_t* M) {
     if (!h || !E || !M) return fail(ISING_EINVAL, "ising_observables: null argument");
     int64_t nw = 0;
     ISING_HIP(launch_observe_single(h->W, h->g, h->partials, &nw, h->stream));
-    ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, nullptr, nullptr, 0, h->d_EM, h->stream));
+    ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, nullptr, nullptr, 0, h->d_EM, h->d_fin, h->stream));
     int64_t em[2];
     ISING_HIP(hipMemcpyAsync(em, h->d_EM, sizeof em, hipMemcpyDeviceToHost, h->stream));
     ISING_HIP(hipStreamSynchronize(h->stream));

@@ -27,9 +27,13 @@ hipError_t launch_halfsweep_single(int wpt, int block, uint64_t* W, const SweepA
 int64_t halfsweep_single_waves(const Geometry& g, int wpt, int block);
 
 // Sum the partials of one lattice into E, M and store them: sample index
-// `idx` of series (if non-null), and out_EM[0..1] (if non-null).
+// `idx` of series (if non-null), and out_EM[0..1] (if non-null).  `scratch`
+// is finalize_scratch_bytes() of device memory, zeroed once before first use
+// (the kernel leaves it ready for the next call); calls sharing a scratch
+// buffer must be ordered on one stream.
+size_t finalize_scratch_bytes();
 hipError_t launch_finalize_single(const Partial* partials, int64_t n_partials, int32_t L, int64_t* series_E,
-                                  int64_t* series_M, int64_t idx, int64_t* out_EM, hipStream_t s);
+                                  int64_t* series_M, int64_t idx, int64_t* out_EM, void* scratch, hipStream_t s);
 
 // Observables of one lattice: per-wavefront partials of right+down
 // antiparallel bonds and up spins over all words.
@@ -45,10 +49,12 @@ hipError_t launch_pack(const uint8_t* in, const Geometry& g, uint64_t* W, hipStr
 
 // ---- batches --------------------------------------------------------------
 
-// Tiled half-sweep over a wave table covering many lattices.
+// Tiled half-sweep over a wave table covering many lattices.  off32: every
+// listed lattice is smaller than 4 GiB (32-bit word offsets).
 hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, const LatticeState* states,
                                   const WaveItem* waves, int64_t n_waves, int colour, uint32_t sweep_off,
-                                  Partial* partials, hipStream_t s);
+                                  Partial* partials, bool off32, hipStream_t s);
+inline bool fits_off32(const Geometry& g) { return (uint64_t)g.N * (uint64_t)g.L * 8u < (1ull << 32); }
 // Per-lattice finalize of a measured sweep for the tiled lattices.
 // Lattices whose sweep_limit is <= sweep_off took no part in that sweep and
 // are skipped.
@@ -64,9 +70,10 @@ hipError_t set_resident_lds(int wpt, size_t lds_bytes);
 hipError_t launch_resident(int wpt, int block, const LatticeDesc* descs, LatticeState* states, const int32_t* ids,
                            int32_t n_ids, int32_t K, int32_t every, size_t lds_bytes, hipStream_t s);
 // Current E and M into states[i].last_E / last_M for the lattices ids[0..n)
-// (ids null: lattices 0..n).
+// (ids null: lattices 0..n), and into out_EM[2k], out_EM[2k+1] for the k-th
+// listed lattice when out_EM is non-null.
 hipError_t launch_observe_multi(const LatticeDesc* descs, LatticeState* states, const int32_t* ids, int32_t n_lat,
-                                hipStream_t s);
+                                int64_t* out_EM, hipStream_t s);
 // Zero the sample accumulators of every lattice; start a call (series_idx = 0).
 hipError_t launch_reset_sums(LatticeState* states, int32_t n_lat, hipStream_t s);
 hipError_t launch_begin_call(LatticeState* states, int32_t n_lat, hipStream_t s);
