@@ -319,7 +319,13 @@ def run_serving(ising, rate=25.0, duration=10.0, quantum=100, seed=2026):
     i = 0
     t0 = time.perf_counter()
     done = 0
+    next_report = 10.0
     while done < len(arrivals):
+        if time.perf_counter() - t0 > next_report:
+            st = srv.stats()
+            log(f"  serving t={time.perf_counter() - t0:.0f}s submitted={i} done={done} queued={st['queued']} "
+                f"resident={st['resident']}")
+            next_report += 10.0
         now = time.perf_counter() - t0
         while i < len(arrivals) and arrivals[i][0] <= now:
             _, r, L, T, sw = arrivals[i]
@@ -353,6 +359,10 @@ def main():
                     help="comma list of secondary workloads, or 'none'")
     ap.add_argument("--serving-rate", type=float, default=25.0)
     ap.add_argument("--serving-duration", type=float, default=10.0)
+    ap.add_argument("--serving-sweep", default="", metavar="RATES",
+                    help="only run the served stream at each comma-separated rate (req/s) for --serving-duration "
+                         "seconds and print one JSON line per rate")
+    ap.add_argument("--serving-quantum", type=int, default=100)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run 10 device-to-device copies of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -372,6 +382,12 @@ def main():
         sys.exit(1)
     ising.load()
     torch.cuda.set_device(0)
+    if args.serving_sweep:
+        for rate in [float(x) for x in args.serving_sweep.split(",")]:
+            log(f"serving at {rate:g} req/s for {args.serving_duration:g} s")
+            print(json.dumps({"rate_req_s": rate, "quantum": args.serving_quantum,
+                              **run_serving(ising, rate, args.serving_duration, args.serving_quantum)}), flush=True)
+        return
     if args.copy_probe:
         src = torch.empty(args.copy_probe // 4, dtype=torch.int32, device="cuda").fill_(1)
         dst = torch.empty_like(src)
@@ -399,7 +415,7 @@ def main():
         elif name == "scan64":
             secondary[name] = run_scan64(ising)
         elif name == "serving":
-            secondary[name] = run_serving(ising, args.serving_rate, args.serving_duration)
+            secondary[name] = run_serving(ising, args.serving_rate, args.serving_duration, args.serving_quantum)
         log(f"  {secondary.get(name)}")
 
     cpu = None
