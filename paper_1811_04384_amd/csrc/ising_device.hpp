@@ -235,13 +235,17 @@ __device__ __forceinline__ void update_segment(const Load& ld, const Store& st, 
         Codes codes = {0u, 0u, 0u};
 #pragma unroll
         for (int g = 0; g < 5; ++g) {
-            U4 r = {0u, 0u, 0u, 0u};  // positions past the last live one are dead slots
-            if (4 * g < n_live)
-                r = philox_lane_c1(a.t_lo, row_base + (uint32_t)J, a.t_hi, (uint32_t)g | (1u << 3), a.k0, a.k1);
-            append_draw(codes, 4 * g + 0, r.x, a.t4, a.t8);
-            append_draw(codes, 4 * g + 1, r.y, a.t4, a.t8);
-            append_draw(codes, 4 * g + 2, r.z, a.t4, a.t8);
-            append_draw(codes, 4 * g + 3, r.w, a.t4, a.t8);
+            if (4 * g < n_live) {
+                const U4 r =
+                    philox_lane_c1(a.t_lo, row_base + (uint32_t)J, a.t_hi, (uint32_t)g | (1u << 3), a.k0, a.k1);
+                append_draw(codes, 4 * g + 0, r.x, a.t4, a.t8);
+                append_draw(codes, 4 * g + 1, r.y, a.t4, a.t8);
+                append_draw(codes, 4 * g + 2, r.z, a.t4, a.t8);
+                append_draw(codes, 4 * g + 3, r.w, a.t4, a.t8);
+            } else {  // positions past the last live one are dead slots: code 0
+#pragma unroll
+                for (int j = 0; j < 4; ++j) append_code(codes, 4 * g + j, 0u);
+            }
         }
         append_draw(codes, 20, u5[k], a.t4, a.t8);  // dead slot when n_live < 21
 
