@@ -147,6 +147,55 @@ def sweep(s, seed, t0, n_sweeps, T, every=0, threads=0):
     return None
 
 
+def moments(Es, Ms):
+    """Exact sums over a sample series, as Python ints: the number of samples,
+    sum E, sum E^2, sum |M|, sum M^2, sum M^4."""
+    Es = [int(e) for e in Es]
+    Ms = [int(m) for m in Ms]
+    return {"n_samples": len(Es), "sum_E": sum(Es), "sum_E2": sum(e * e for e in Es),
+            "sum_absM": sum(abs(m) for m in Ms), "sum_M2": sum(m * m for m in Ms),
+            "sum_M4": sum(m ** 4 for m in Ms)}
+
+
+def scan(L, seed, hot, Ts, therm, meas, every=1, threads=0, state=None, t0=0):
+    """Temperature scan with the lattice carried over, the paper's driver
+    loop (Section 5: the temperature is stepped while the lattice is kept,
+    and the energies of the iterations at each temperature are averaged,
+    Section 2, Eq. 2): at each T in order, ``therm`` sweeps without samples,
+    then ``meas`` sweeps sampled after every ``every``-th.
+
+    Returns (list of moments dicts, final state, next sweep index)."""
+    s = init(L, seed, hot) if state is None else state
+    t = int(t0)
+    out = []
+    for T in Ts:
+        sweep(s, seed, t, therm, T, threads=threads)
+        t += int(therm)
+        Es, Ms = sweep(s, seed, t, meas, T, every, threads=threads)
+        t += int(meas)
+        out.append(moments(Es, Ms))
+    return out, s, t
+
+
+def thermodynamics(m, L, T):
+    """Per-spin canonical averages from exact moment sums (k_B = J = 1), in
+    exact rational arithmetic rounded once: e = <E>/L^2 (Eq. 2 per spin),
+    c = (<E^2> - <E>^2)/(T^2 L^2), |m| = <|M|>/L^2,
+    chi = (<M^2> - <|M|>^2)/(T L^2), binder = 1 - <M^4>/(3 <M^2>^2)."""
+    from fractions import Fraction
+
+    n = m["n_samples"]
+    if n < 1:
+        raise ValueError("no samples")
+    N = Fraction(L * L)
+    T = Fraction(float(T))
+    E1, E2 = Fraction(m["sum_E"], n), Fraction(m["sum_E2"], n)
+    A1, M2, M4 = Fraction(m["sum_absM"], n), Fraction(m["sum_M2"], n), Fraction(m["sum_M4"], n)
+    return {"e": float(E1 / N), "c": float((E2 - E1 * E1) / (T * T * N)), "abs_m": float(A1 / N),
+            "chi": float((M2 - A1 * A1) / (T * N)),
+            "binder": float(1 - M4 / (3 * M2 * M2)) if M2 else float("nan")}
+
+
 def init_window(L, seed, hot, r0, c0, h, w):
     win = np.empty((h, w), dtype=np.uint8)
     if _load().oracle_init_window(int(L), int(seed), int(bool(hot)), int(r0), int(c0), int(h), int(w),

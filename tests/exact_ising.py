@@ -12,6 +12,10 @@ to pin the oracle's Markov chain to the physics it must sample.
       cosh g_k = cosh 2K coth 2K - cos(pi k / L) (k >= 1),
       g_0 = 2K + ln tanh K,
   and e = -(1/L^2) d ln Z / dK.
+- brute_force_moments(L, T): exact canonical averages <E>, <E^2>, <|M|>,
+  <M^2>, <M^4> (whole-lattice E, M) by the same enumeration.
+- kaufman_specific_heat(L, T): exact specific heat per spin of the finite
+  torus, c = K^2 d^2 ln Z / dK^2 / L^2 (K = 1/T), from the same Z.
 - onsager_energy(T): Onsager's infinite-lattice energy per spin,
       u = -coth 2K [1 + (2/pi)(2 tanh^2 2K - 1) K1(kappa)],
       kappa = 2 sinh 2K / cosh^2 2K.
@@ -38,6 +42,30 @@ def brute_force(L, T):
     e = (w * E).sum() / Z / n
     am = (w * np.abs(M)).sum() / Z / n
     return float(e), float(am)
+
+
+def brute_force_moments(L, T):
+    n = L * L
+    idx = np.arange(1 << n, dtype=np.uint32)
+    spins = ((idx[:, None] >> np.arange(n, dtype=np.uint32)[None, :]) & 1).astype(np.int8) * 2 - 1
+    s = spins.reshape(-1, L, L).astype(np.int32)
+    E = (-(s * np.roll(s, -1, axis=2)).sum(axis=(1, 2)) - (s * np.roll(s, -1, axis=1)).sum(axis=(1, 2))).astype(
+        np.float64)
+    M = s.sum(axis=(1, 2)).astype(np.float64)
+    w = np.exp(-(E - E.min()) / T)
+    Z = w.sum()
+
+    def avg(x):
+        return float((w * x).sum() / Z)
+
+    return {"E": avg(E), "E2": avg(E * E), "absM": avg(np.abs(M)), "M2": avg(M * M), "M4": avg(M ** 4)}
+
+
+def kaufman_specific_heat(L, T, dps=60):
+    with mpmath.workdps(dps):
+        K = 1 / mpmath.mpf(T)
+        d2 = mpmath.diff(lambda k: _lnZ(L, k), K, 2)
+        return float(K * K * d2 / (L * L))
 
 
 def _lnZ(L, K):
