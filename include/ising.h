@@ -73,6 +73,38 @@ enum {
 };
 enum { ISING_COLD = 0, ISING_HOT = 1 };
 
+/* Exact sums over sampled states (E_k, M_k), k = 1..n_samples.  The wide
+   sums are unsigned little-endian 64-bit limbs (value = sum_j limb[j] 2^(64j)).
+   Exact for every L <= 2^18 while n_samples < 2^26 (sum_E, sum_absM) and
+   n_samples < 2^48 (the wide sums). */
+typedef struct {
+    int64_t n_samples;
+    int64_t sum_E;       /* sum of E                  */
+    uint64_t sum_E2[2];  /* sum of E^2, 128 bits      */
+    int64_t sum_absM;    /* sum of |M|                */
+    uint64_t sum_M2[2];  /* sum of M^2, 128 bits      */
+    uint64_t sum_M4[3];  /* sum of M^4, 192 bits      */
+} ising_moments;
+
+/* Per-spin thermodynamics of one set of moments at temperature T on L x L
+   spins (k_B = J = 1), <x> = sum x / n_samples:
+     e      = <E> / L^2                          (the paper's average energy,
+                                                  Section 2, Eq. 2, per spin)
+     c      = (<E^2> - <E>^2) / (T^2 L^2)        specific heat
+     abs_m  = <|M|> / L^2
+     chi    = (<M^2> - <|M|>^2) / (T L^2)        susceptibility
+     binder = 1 - <M^4> / (3 <M^2>^2)            Binder cumulant
+   The fluctuation formulas are the standard canonical-ensemble ones; the
+   paper itself reports only e. */
+typedef struct {
+    double e, c, abs_m, chi, binder;
+} ising_thermo;
+
+/* ising_thermodynamics: host arithmetic only (long double), no device work.
+   EINVAL for NULL pointers, n_samples < 1, invalid L or T.  binder is NaN
+   when <M^2> = 0. */
+int ising_thermodynamics(const ising_moments* m, int32_t L, double T, ising_thermo* out);
+
 typedef struct ising_lattice ising_lattice; /* one lattice (opaque)                 */
 typedef struct ising_batch ising_batch;     /* many lattices, one launch per phase  */
 typedef struct ising_server ising_server;   /* continuous-batching request server   */
@@ -132,6 +164,22 @@ int ising_sweep(ising_lattice* h, double T, int64_t n_sweeps);
    into the second half of the sampled sweep.  every >= 1. */
 int ising_sweep_measure(ising_lattice* h, double T, int64_t n_sweeps, int32_t every, int64_t* dev_E,
                         int64_t* dev_M);
+
+/* As ising_sweep_measure, but every sampled (E, M) is added to the moment
+   sums *dev_acc (a device pointer to one ising_moments, which the caller
+   zeroes before the first call and may keep adding to) instead of a series. */
+int ising_sweep_moments(ising_lattice* h, double T, int64_t n_sweeps, int32_t every, ising_moments* dev_acc);
+
+/* Temperature scan with the lattice carried over from one temperature to
+   the next, the paper's driver loop (Section 5: the program steps the
+   temperature and keeps the lattice, averaging the energy of the iterations
+   at each temperature): for i = 0..n_T-1, therm >= 0 sweeps at T[i] without
+   sampling, then meas >= 0 sweeps at T[i] sampled after every every-th
+   (every >= 1), whose moments are stored in out[i] (host array of n_T).  An
+   ascending T is a heating scan, a descending one a cooling scan.  Advances
+   the sweep counter by n_T (therm + meas).  Synchronises. */
+int ising_scan(ising_lattice* h, int32_t n_T, const double* T, int64_t therm, int64_t meas, int32_t every,
+               ising_moments* out);
 
 /* E and M of the current state (host pointers).  Synchronises the stream. */
 int ising_observables(ising_lattice* h, int64_t* E, int64_t* M);
@@ -200,6 +248,19 @@ int ising_batch_sweep(ising_batch* b, const double* T, int64_t n_sweeps, int32_t
 int ising_batch_results(ising_batch* b, int64_t* E, int64_t* M, int64_t* sum_E, int64_t* sum_absM,
                         int64_t* n_samples);
 int ising_batch_reset_sums(ising_batch* b);
+
+/* Per-lattice moment sums over the same samples as ising_batch_results
+   (host array of n).  Synchronises. */
+int ising_batch_moments(ising_batch* b, ising_moments* out);
+
+/* Temperature scan of every lattice of the batch at once, each carried over
+   from one temperature to the next: for step j = 0..n_T-1 every lattice i
+   takes therm sweeps at T[j*n + i] without sampling, then meas sweeps sampled
+   after every every-th (every >= 1), whose moments go to out[j*n + i] (host
+   arrays of n_T*n).  The running sums of ising_batch_results are reset at
+   each step and hold the last step's samples afterwards.  Synchronises. */
+int ising_batch_scan(ising_batch* b, int32_t n_T, const double* T, int64_t therm, int64_t meas, int32_t every,
+                     ising_moments* out);
 
 /* Spins of lattice i (host array of L[i]^2 bytes); sweep counter of i. */
 int ising_batch_get_spins(ising_batch* b, int32_t i, uint8_t* host_spins);

@@ -16,10 +16,10 @@ import numpy as np
 
 from . import _lib
 from ._lib import (ISING_COLD, ISING_EAGAIN, ISING_EBUSY, ISING_EHIP, ISING_EINVAL, ISING_ENOMEM, ISING_HOT, ISING_OK,
-                   BatchPlan, Result)
+                   BatchPlan, Moments, Result, Thermo)
 
 __all__ = [
-    "IsingError", "Lattice", "Batch", "Server", "BatchPlan", "Result", "load",
+    "IsingError", "Lattice", "Batch", "Server", "BatchPlan", "Result", "Moments", "Thermo", "load", "moments_of",
     "ISING_OK", "ISING_EINVAL", "ISING_ENOMEM", "ISING_EHIP", "ISING_EBUSY", "ISING_EAGAIN", "ISING_COLD", "ISING_HOT",
 ] + sorted(_lib.SIGNATURES)
 
@@ -123,6 +123,45 @@ def ising_sweep_measure(h, T, n_sweeps, every, dev_E, dev_M):
     _check(_lib.load().ising_sweep_measure(h, float(T), int(n_sweeps), int(every), _ptr(dev_E), _ptr(dev_M)))
 
 
+def ising_sweep_moments(h, T, n_sweeps, every, dev_acc):
+    """dev_acc: device memory of one ising_moments (e.g. torch.zeros(10, dtype=torch.int64, device='cuda'))."""
+    _check(_lib.load().ising_sweep_moments(h, float(T), int(n_sweeps), int(every), _ptr(dev_acc)))
+
+
+def ising_scan(h, T, therm, meas, every):
+    """Heating/cooling scan over the temperatures T (lattice carried over);
+    one moments dict (exact Python ints) per temperature."""
+    T_, pT = _arr(T, ctypes.c_double)
+    out = (Moments * max(1, len(T_)))()
+    _check(_lib.load().ising_scan(h, len(T_), pT, int(therm), int(meas), int(every), out))
+    return [out[i].as_dict() for i in range(len(T_))]
+
+
+def moments_of(acc):
+    """Moments dict of a device accumulator filled by ising_sweep_moments."""
+    raw = acc.detach().cpu().contiguous().numpy().tobytes() if hasattr(acc, "detach") else bytes(acc)
+    return Moments.from_buffer_copy(raw[:ctypes.sizeof(Moments)]).as_dict()
+
+
+def _moments_struct(m):
+    if isinstance(m, Moments):
+        return m
+    out = Moments()
+    out.n_samples, out.sum_E, out.sum_absM = int(m["n_samples"]), int(m["sum_E"]), int(m["sum_absM"])
+    for name, limbs in (("sum_E2", 2), ("sum_M2", 2), ("sum_M4", 3)):
+        v = int(m[name])
+        for j in range(limbs):
+            getattr(out, name)[j] = (v >> (64 * j)) & 0xFFFFFFFFFFFFFFFF
+    return out
+
+
+def ising_thermodynamics(m, L, T):
+    """Per-spin e, c, |m|, chi, Binder cumulant of one moments dict (host arithmetic in the library)."""
+    out = Thermo()
+    _check(_lib.load().ising_thermodynamics(ctypes.byref(_moments_struct(m)), int(L), float(T), ctypes.byref(out)))
+    return out.as_dict()
+
+
 def ising_observables(h):
     E, M = ctypes.c_int64(), ctypes.c_int64()
     _check(_lib.load().ising_observables(h, ctypes.byref(E), ctypes.byref(M)))
@@ -209,6 +248,22 @@ def ising_batch_results(h, n):
 
 def ising_batch_reset_sums(h):
     _check(_lib.load().ising_batch_reset_sums(h))
+
+
+def ising_batch_moments(h, n):
+    out = (Moments * n)()
+    _check(_lib.load().ising_batch_moments(h, out))
+    return [out[i].as_dict() for i in range(n)]
+
+
+def ising_batch_scan(h, n, T, therm, meas, every):
+    """T: (n_T, n) temperatures, row j for step j; returns n_T lists of n moments dicts."""
+    T_ = np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(-1, n))
+    n_T = T_.shape[0]
+    out = (Moments * max(1, n_T * n))()
+    _check(_lib.load().ising_batch_scan(h, n_T, T_.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(therm),
+                                        int(meas), int(every), out))
+    return [[out[j * n + i].as_dict() for i in range(n)] for j in range(n_T)]
 
 
 def ising_batch_get_spins(h, i, L):
@@ -318,6 +373,18 @@ class Lattice:
         ising_sweep_measure(self.handle, T, n, every, E, M)
         return E[:k], M[:k]
 
+    def sweep_moments(self, T, n, every, acc=None):
+        """Adds the samples' moments to `acc` (a device int64 tensor of 10, zeroed if None) and returns it."""
+        import torch
+
+        if acc is None:
+            acc = torch.zeros(10, dtype=torch.int64, device=self.words.device)
+        ising_sweep_moments(self.handle, T, n, every, acc)
+        return acc
+
+    def scan(self, T, therm, meas, every=1):
+        return ising_scan(self.handle, T, therm, meas, every)
+
     def observables(self):
         return ising_observables(self.handle)
 
@@ -392,6 +459,16 @@ class Batch:
 
     def reset_sums(self):
         ising_batch_reset_sums(self.handle)
+
+    def moments(self):
+        return ising_batch_moments(self.handle, len(self.Ls))
+
+    def scan(self, T, therm, meas, every=1):
+        """T: one temperature per step (shared by all lattices) or an (n_T, n) array."""
+        T = np.asarray(T, dtype=np.float64)
+        if T.ndim == 1:
+            T = np.repeat(T[:, None], len(self.Ls), axis=1)
+        return ising_batch_scan(self.handle, len(self.Ls), T, therm, meas, every)
 
     def spins(self, i):
         return ising_batch_get_spins(self.handle, i, self.Ls[i])

@@ -27,6 +27,24 @@ class Result(ctypes.Structure):
                 ("E", c_i64), ("M", c_i64), ("t_submit_s", c_dbl), ("t_admit_s", c_dbl), ("t_done_s", c_dbl)]
 
 
+class Moments(ctypes.Structure):
+    _fields_ = [("n_samples", c_i64), ("sum_E", c_i64), ("sum_E2", c_u64 * 2), ("sum_absM", c_i64),
+                ("sum_M2", c_u64 * 2), ("sum_M4", c_u64 * 3)]
+
+    def as_dict(self):
+        def wide(limbs):
+            return sum(int(v) << (64 * j) for j, v in enumerate(limbs))
+        return {"n_samples": int(self.n_samples), "sum_E": int(self.sum_E), "sum_E2": wide(self.sum_E2),
+                "sum_absM": int(self.sum_absM), "sum_M2": wide(self.sum_M2), "sum_M4": wide(self.sum_M4)}
+
+
+class Thermo(ctypes.Structure):
+    _fields_ = [("e", c_dbl), ("c", c_dbl), ("abs_m", c_dbl), ("chi", c_dbl), ("binder", c_dbl)]
+
+    def as_dict(self):
+        return {k: float(getattr(self, k)) for k, _ in self._fields_}
+
+
 # name -> (restype, argtypes); every entry point declared in include/ising.h
 SIGNATURES = {
     "ising_word_rows": (c_i32, [c_i32]),
@@ -40,6 +58,9 @@ SIGNATURES = {
     "ising_destroy": (c_int, [c_vp]),
     "ising_sweep": (c_int, [c_vp, c_dbl, c_i64]),
     "ising_sweep_measure": (c_int, [c_vp, c_dbl, c_i64, c_i32, c_vp, c_vp]),
+    "ising_sweep_moments": (c_int, [c_vp, c_dbl, c_i64, c_i32, c_vp]),
+    "ising_scan": (c_int, [c_vp, c_i32, P(c_dbl), c_i64, c_i64, c_i32, P(Moments)]),
+    "ising_thermodynamics": (c_int, [P(Moments), c_i32, c_dbl, P(Thermo)]),
     "ising_observables": (c_int, [c_vp, P(c_i64), P(c_i64)]),
     "ising_get_spins": (c_int, [c_vp, c_vp]),
     "ising_get_spins_region": (c_int, [c_vp, c_i32, c_i32, c_i32, c_i32, c_vp]),
@@ -56,6 +77,8 @@ SIGNATURES = {
     "ising_batch_sweep": (c_int, [c_vp, P(c_dbl), c_i64, c_i32, c_vp, c_vp]),
     "ising_batch_results": (c_int, [c_vp, P(c_i64), P(c_i64), P(c_i64), P(c_i64), P(c_i64)]),
     "ising_batch_reset_sums": (c_int, [c_vp]),
+    "ising_batch_moments": (c_int, [c_vp, P(Moments)]),
+    "ising_batch_scan": (c_int, [c_vp, c_i32, P(c_dbl), c_i64, c_i64, c_i32, P(Moments)]),
     "ising_batch_get_spins": (c_int, [c_vp, c_i32, c_vp]),
     "ising_batch_get_sweep_count": (c_int, [c_vp, c_i32, P(c_u64)]),
     "ising_batch_set_plan": (c_int, [c_vp, P(BatchPlan)]),

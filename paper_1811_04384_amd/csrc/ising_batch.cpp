@@ -491,9 +491,9 @@ int ising_batch_results(ising_batch* b, int64_t* E, int64_t* M, int64_t* sum_E, 
     for (int32_t i = 0; i < b->n; ++i) {
         if (E) E[i] = st[i].last_E;
         if (M) M[i] = st[i].last_M;
-        if (sum_E) sum_E[i] = st[i].sum_E;
-        if (sum_absM) sum_absM[i] = st[i].sum_absM;
-        if (n_samples) n_samples[i] = st[i].n_samples;
+        if (sum_E) sum_E[i] = st[i].mom.sum_E;
+        if (sum_absM) sum_absM[i] = st[i].mom.sum_absM;
+        if (n_samples) n_samples[i] = st[i].mom.n;
     }
     return ISING_OK;
 }
@@ -501,6 +501,37 @@ int ising_batch_results(ising_batch* b, int64_t* E, int64_t* M, int64_t* sum_E, 
 int ising_batch_reset_sums(ising_batch* b) {
     if (!b) return fail(ISING_EINVAL, "ising_batch_reset_sums: null handle");
     ISING_HIP(launch_reset_sums(b->d_state, b->n, b->stream));
+    return ISING_OK;
+}
+
+int ising_batch_moments(ising_batch* b, ising_moments* out) {
+    if (!b || !out) return fail(ISING_EINVAL, "ising_batch_moments: null argument");
+    std::vector<LatticeState> st(b->n);
+    ISING_HIP(hipMemcpyAsync(st.data(), b->d_state, sizeof(LatticeState) * b->n, hipMemcpyDeviceToHost, b->stream));
+    ISING_HIP(hipStreamSynchronize(b->stream));
+    for (int32_t i = 0; i < b->n; ++i) std::memcpy(&out[i], &st[i].mom, sizeof(ising_moments));
+    return ISING_OK;
+}
+
+int ising_batch_scan(ising_batch* b, int32_t n_T, const double* T, int64_t therm, int64_t meas, int32_t every,
+                     ising_moments* out) {
+    if (!b) return fail(ISING_EINVAL, "ising_batch_scan: null handle");
+    if (n_T < 0 || therm < 0 || meas < 0 || every < 1)
+        return fail(ISING_EINVAL, "ising_batch_scan: need n_T, therm, meas >= 0 and every >= 1");
+    if (n_T > 0 && (!T || !out)) return fail(ISING_EINVAL, "ising_batch_scan: null array");
+    for (int64_t k = 0; k < (int64_t)n_T * b->n; ++k)
+        if (!valid_T(T[k])) return fail(ISING_EINVAL, "ising_batch_scan: T[%lld] = %g is not finite and > 0",
+                                        (long long)k, T[k]);
+    for (int32_t j = 0; j < n_T; ++j) {
+        const double* Tj = T + (size_t)j * b->n;
+        int rc = sweep_impl(b, Tj, therm, 0, nullptr, nullptr);
+        if (rc != ISING_OK) return rc;
+        ISING_HIP(launch_reset_sums(b->d_state, b->n, b->stream));
+        rc = sweep_impl(b, Tj, meas, every, nullptr, nullptr);
+        if (rc != ISING_OK) return rc;
+        rc = ising_batch_moments(b, out + (size_t)j * b->n);
+        if (rc != ISING_OK) return rc;
+    }
     return ISING_OK;
 }
 

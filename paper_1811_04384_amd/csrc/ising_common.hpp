@@ -54,14 +54,23 @@ struct LatticeDesc {
     int64_t* series_M;
 };
 
+// Exact sums over sampled (E, M): the wide ones in little-endian 64-bit
+// limbs.  Same layout as ising_moments of the C interface.
+struct Moments {
+    int64_t n;             // samples
+    int64_t sum_E;         // sum of E
+    uint64_t sum_E2[2];    // sum of E^2 (128 bits)
+    int64_t sum_absM;      // sum of |M|
+    uint64_t sum_M2[2];    // sum of M^2 (128 bits)
+    uint64_t sum_M4[3];    // sum of M^4 (192 bits)
+};
+
 // Per-lattice state of a batch, written only by kernels (the host reads it
 // back and zeroes it at creation).
 struct LatticeState {
     uint64_t t;               // absolute index of the next sweep
     int64_t series_idx;       // next sample slot of the current call
-    int64_t n_samples;        // accumulated samples
-    int64_t sum_E;            // sum of E over samples
-    int64_t sum_absM;         // sum of |M| over samples
+    Moments mom;              // sums over the samples since the last reset
     int64_t last_E, last_M;   // most recent sample or observation
 };
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
@@ -13,6 +14,12 @@
 #include "ising_common.hpp"
 
 namespace ising {
+
+// The device-side moment sums are handed out as ising_moments unchanged.
+static_assert(sizeof(Moments) == sizeof(ising_moments), "Moments layout");
+static_assert(offsetof(Moments, sum_E2) == offsetof(ising_moments, sum_E2), "Moments layout");
+static_assert(offsetof(Moments, sum_absM) == offsetof(ising_moments, sum_absM), "Moments layout");
+static_assert(offsetof(Moments, sum_M4) == offsetof(ising_moments, sum_M4), "Moments layout");
 
 std::string& last_error_ref();
 

@@ -165,6 +165,40 @@ __device__ __forceinline__ void energy_magnetisation(uint64_t anti, uint64_t ups
     M = 2 * (int64_t)ups - n;
 }
 
+// Adds the sample (E, M) to exact moment sums.  For L <= 2^18, |E| <= 2 L^2
+// <= 2^37 and |M| <= L^2 = 2^36, so E^2 and M^2 fit 128 bits; M^4 < 2^144 is
+// formed in three limbs from q = M^2 = qh 2^64 + ql (qh < 2^8):
+// q^2 = ql^2 + 2 ql qh 2^64 + qh^2 2^128.
+__device__ inline void add128(uint64_t* s, unsigned __int128 x) {
+    unsigned __int128 v = ((unsigned __int128)s[1] << 64) | s[0];
+    v += x;
+    s[0] = (uint64_t)v;
+    s[1] = (uint64_t)(v >> 64);
+}
+
+__device__ inline void add_sample(Moments& m, int64_t E, int64_t M) {
+    typedef unsigned __int128 u128;
+    const uint64_t aE = E < 0 ? 0ull - (uint64_t)E : (uint64_t)E;
+    const uint64_t aM = M < 0 ? 0ull - (uint64_t)M : (uint64_t)M;
+    m.n += 1;
+    m.sum_E += E;
+    m.sum_absM += (int64_t)aM;
+    add128(m.sum_E2, (u128)aE * aE);
+    const u128 q = (u128)aM * aM;
+    add128(m.sum_M2, q);
+    const uint64_t ql = (uint64_t)q, qh = (uint64_t)(q >> 64);
+    const u128 p0 = (u128)ql * ql;
+    const u128 p1 = ((u128)ql * qh) << 1;
+    const u128 mid = (p0 >> 64) + (uint64_t)p1;
+    const uint64_t l0 = (uint64_t)p0, l1 = (uint64_t)mid;
+    const uint64_t l2 = (uint64_t)(mid >> 64) + (uint64_t)(p1 >> 64) + qh * qh;
+    const u128 a = (u128)m.sum_M4[0] + l0;
+    const u128 b = (u128)m.sum_M4[1] + l1 + (uint64_t)(a >> 64);
+    m.sum_M4[0] = (uint64_t)a;
+    m.sum_M4[1] = (uint64_t)b;
+    m.sum_M4[2] += l2 + (uint64_t)(b >> 64);
+}
+
 // Grid reduction of one lattice's wavefront partials: every workgroup sums a
 // slice into block_sums[blockIdx.x]; the last workgroup to finish (ticket
 // counter at device scope) adds the slices, turns them into E, M and resets
@@ -173,7 +207,7 @@ constexpr int kFinalizeBlocks = 256;
 
 __global__ void __launch_bounds__(256) k_finalize_single(const Partial* __restrict__ partials, int64_t n_partials,
                                                          int32_t L, int64_t* series_E, int64_t* series_M,
-                                                         int64_t idx, int64_t* out_EM,
+                                                         int64_t idx, int64_t* out_EM, Moments* mom,
                                                          unsigned long long* __restrict__ block_sums,
                                                          unsigned int* __restrict__ ticket) {
     __shared__ uint64_t red[32];
@@ -210,6 +244,7 @@ __global__ void __launch_bounds__(256) k_finalize_single(const Partial* __restri
             out_EM[0] = E;
             out_EM[1] = M;
         }
+        if (mom) add_sample(*mom, E, M);
         *ticket = 0u;
     }
 }
@@ -233,12 +268,10 @@ __global__ void __launch_bounds__(256) k_finalize_multi(const LatticeDesc* __res
         const int64_t idx = st.series_idx;
         st.last_E = E;
         st.last_M = M;
-        st.sum_E += E;
-        st.sum_absM += M < 0 ? -M : M;
+        add_sample(st.mom, E, M);
         if (d.series_E) d.series_E[idx] = E;
         if (d.series_M) d.series_M[idx] = M;
         st.series_idx = idx + 1;
-        st.n_samples += 1;
     }
 }
 
@@ -250,11 +283,7 @@ __global__ void k_advance(const LatticeDesc* __restrict__ descs, LatticeState* _
 
 __global__ void k_reset_sums(LatticeState* __restrict__ states, int32_t n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        states[i].n_samples = 0;
-        states[i].sum_E = 0;
-        states[i].sum_absM = 0;
-    }
+    if (i < n) states[i].mom = Moments{};
 }
 
 __global__ void k_begin_call(LatticeState* __restrict__ states, int32_t n) {
@@ -291,14 +320,13 @@ __global__ void __launch_bounds__(kResidentMaxBlock)
     const uint64_t t0 = state.t;
     const int32_t n_sweeps = min(K, d.sweep_limit);
     // sample accumulators stay in thread 0's registers for the whole launch
-    int64_t series_idx = 0, n_samples = 0, sum_E = 0, sum_absM = 0, last_E = 0, last_M = 0;
+    int64_t series_idx = 0, last_E = 0, last_M = 0;
+    Moments mom = {};
     int64_t* const series_E = d.series_E;
     int64_t* const series_M = d.series_M;
     if (threadIdx.x == 0) {
         series_idx = state.series_idx;
-        n_samples = state.n_samples;
-        sum_E = state.sum_E;
-        sum_absM = state.sum_absM;
+        mom = state.mom;
         last_E = state.last_E;
         last_M = state.last_M;
     }
@@ -324,21 +352,17 @@ __global__ void __launch_bounds__(kResidentMaxBlock)
                     energy_magnetisation(A, U, L, E, M);
                     last_E = E;
                     last_M = M;
-                    sum_E += E;
-                    sum_absM += M < 0 ? -M : M;
+                    add_sample(mom, E, M);
                     if (series_E) series_E[series_idx] = E;
                     if (series_M) series_M[series_idx] = M;
                     series_idx += 1;
-                    n_samples += 1;
                 }
             }
         }
     }
     if (threadIdx.x == 0) {
         state.series_idx = series_idx;
-        state.n_samples = n_samples;
-        state.sum_E = sum_E;
-        state.sum_absM = sum_absM;
+        state.mom = mom;
         state.last_E = last_E;
         state.last_M = last_M;
     }
@@ -484,13 +508,14 @@ hipError_t launch_halfsweep_single(int wpt, int block, uint64_t* W, const SweepA
 size_t finalize_scratch_bytes() { return 2 * kFinalizeBlocks * sizeof(unsigned long long) + 256; }
 
 hipError_t launch_finalize_single(const Partial* partials, int64_t n_partials, int32_t L, int64_t* series_E,
-                                  int64_t* series_M, int64_t idx, int64_t* out_EM, void* scratch, hipStream_t s) {
+                                  int64_t* series_M, int64_t idx, int64_t* out_EM, Moments* mom, void* scratch,
+                                  hipStream_t s) {
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kFinalizeBlocks, (n_partials + 2047) / 2048));
     unsigned long long* sums = reinterpret_cast<unsigned long long*>(scratch);
     unsigned int* ticket = reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(scratch) +
                                                            2 * kFinalizeBlocks * sizeof(unsigned long long));
     hipLaunchKernelGGL(k_finalize_single, dim3(blocks), dim3(256), 0, s, partials, n_partials, L, series_E, series_M,
-                       idx, out_EM, sums, ticket);
+                       idx, out_EM, mom, sums, ticket);
     return hipGetLastError();
 }
 

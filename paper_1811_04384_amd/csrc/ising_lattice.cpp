@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <vector>
 
@@ -172,7 +173,7 @@ static SweepArgs sweep_args(const ising_lattice* h, uint64_t t, uint32_t t4, uin
 // Enqueue n sweeps of lattice words W (the handle's or a scratch copy)
 // starting at absolute sweep t0.
 static int enqueue_sweeps(const ising_lattice* h, uint64_t* W, uint64_t t0, double T, int64_t n, int32_t every,
-                          int64_t* dev_E, int64_t* dev_M, int wpt, int block) {
+                          int64_t* dev_E, int64_t* dev_M, Moments* mom, int wpt, int block) {
     uint32_t t4, t8;
     thresholds_of(T, &t4, &t8);
     for (int64_t k = 1; k <= n; ++k) {
@@ -182,17 +183,18 @@ static int enqueue_sweeps(const ising_lattice* h, uint64_t* W, uint64_t t0, doub
         int64_t nw = 0;
         ISING_HIP(launch_halfsweep_single(wpt, block, W, a, 1, meas ? h->partials : nullptr, &nw, h->stream));
         if (meas)
-            ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, dev_E, dev_M, k / every - 1, nullptr, h->d_fin,
-                                             h->stream));
+            ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, dev_E, dev_M, k / every - 1, nullptr, mom,
+                                             h->d_fin, h->stream));
     }
     return ISING_OK;
 }
 
-static int sweep_impl(ising_lattice* h, double T, int64_t n, int32_t every, int64_t* dev_E, int64_t* dev_M) {
+static int sweep_impl(ising_lattice* h, double T, int64_t n, int32_t every, int64_t* dev_E, int64_t* dev_M,
+                      Moments* mom = nullptr) {
     if (!h) return fail(ISING_EINVAL, "ising_sweep: null handle");
     if (!valid_T(T)) return fail(ISING_EINVAL, "ising_sweep: T must be finite and > 0 (got %g)", T);
     if (n < 0) return fail(ISING_EINVAL, "ising_sweep: n_sweeps must be >= 0");
-    int rc = enqueue_sweeps(h, h->W, h->t, T, n, every, dev_E, dev_M, h->wpt, h->block);
+    int rc = enqueue_sweeps(h, h->W, h->t, T, n, every, dev_E, dev_M, mom, h->wpt, h->block);
     if (rc != ISING_OK) return rc;
     h->t += (uint64_t)n;
     return ISING_OK;
@@ -207,11 +209,69 @@ int ising_sweep_measure(ising_lattice* h, double T, int64_t n_sweeps, int32_t ev
     return sweep_impl(h, T, n_sweeps, every, dev_E, dev_M);
 }
 
+int ising_sweep_moments(ising_lattice* h, double T, int64_t n_sweeps, int32_t every, ising_moments* dev_acc) {
+    if (every < 1) return fail(ISING_EINVAL, "ising_sweep_moments: every must be >= 1");
+    if (!dev_acc) return fail(ISING_EINVAL, "ising_sweep_moments: null accumulator");
+    return sweep_impl(h, T, n_sweeps, every, nullptr, nullptr, reinterpret_cast<Moments*>(dev_acc));
+}
+
+int ising_scan(ising_lattice* h, int32_t n_T, const double* T, int64_t therm, int64_t meas, int32_t every,
+               ising_moments* out) {
+    if (!h) return fail(ISING_EINVAL, "ising_scan: null handle");
+    if (n_T < 0 || therm < 0 || meas < 0 || every < 1)
+        return fail(ISING_EINVAL, "ising_scan: need n_T, therm, meas >= 0 and every >= 1");
+    if (n_T == 0) return ISING_OK;
+    if (!T || !out) return fail(ISING_EINVAL, "ising_scan: null array");
+    for (int32_t i = 0; i < n_T; ++i)
+        if (!valid_T(T[i])) return fail(ISING_EINVAL, "ising_scan: T[%d] = %g is not finite and > 0", i, T[i]);
+    Moments* d = nullptr;
+    ISING_HIP(hipMalloc(&d, sizeof(Moments) * (size_t)n_T));
+    hipError_t e = hipMemsetAsync(d, 0, sizeof(Moments) * (size_t)n_T, h->stream);
+    int rc = e == hipSuccess ? ISING_OK : hip_fail(e, "hipMemsetAsync");
+    for (int32_t i = 0; i < n_T && rc == ISING_OK; ++i) {
+        rc = sweep_impl(h, T[i], therm, 0, nullptr, nullptr);
+        if (rc == ISING_OK) rc = sweep_impl(h, T[i], meas, every, nullptr, nullptr, d + i);
+    }
+    if (rc == ISING_OK) {
+        e = hipMemcpyAsync(out, d, sizeof(Moments) * (size_t)n_T, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "ising_scan read-back");
+    } else {
+        (void)hipStreamSynchronize(h->stream);
+    }
+    e = hipFree(d);
+    if (rc == ISING_OK && e != hipSuccess) rc = hip_fail(e, "hipFree");
+    return rc;
+}
+
+int ising_thermodynamics(const ising_moments* m, int32_t L, double T, ising_thermo* out) {
+    if (!m || !out) return fail(ISING_EINVAL, "ising_thermodynamics: null argument");
+    if (!valid_L(L)) return fail(ISING_EINVAL, "ising_thermodynamics: invalid L %d", L);
+    if (!valid_T(T)) return fail(ISING_EINVAL, "ising_thermodynamics: T must be finite and > 0 (got %g)", T);
+    if (m->n_samples < 1) return fail(ISING_EINVAL, "ising_thermodynamics: no samples");
+    typedef long double ld;
+    const ld two64 = 18446744073709551616.0L;
+    const ld n = (ld)m->n_samples, spins = (ld)L * (ld)L;
+    const ld E1 = (ld)m->sum_E / n;
+    const ld E2 = ((ld)m->sum_E2[0] + (ld)m->sum_E2[1] * two64) / n;
+    const ld A1 = (ld)m->sum_absM / n;
+    const ld M2 = ((ld)m->sum_M2[0] + (ld)m->sum_M2[1] * two64) / n;
+    const ld M4 = ((ld)m->sum_M4[0] + ((ld)m->sum_M4[1] + (ld)m->sum_M4[2] * two64) * two64) / n;
+    const ld t = (ld)T;
+    out->e = (double)(E1 / spins);
+    out->c = (double)((E2 - E1 * E1) / (t * t * spins));
+    out->abs_m = (double)(A1 / spins);
+    out->chi = (double)((M2 - A1 * A1) / (t * spins));
+    out->binder = M2 > 0 ? (double)(1.0L - M4 / (3.0L * M2 * M2)) : std::numeric_limits<double>::quiet_NaN();
+    return ISING_OK;
+}
+
 int ising_observables(ising_lattice* h, int64_t* E, int64_t* M) {
     if (!h || !E || !M) return fail(ISING_EINVAL, "ising_observables: null argument");
     int64_t nw = 0;
     ISING_HIP(launch_observe_single(h->W, h->g, h->partials, &nw, h->stream));
-    ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, nullptr, nullptr, 0, h->d_EM, h->d_fin, h->stream));
+    ISING_HIP(launch_finalize_single(h->partials, nw, h->g.L, nullptr, nullptr, 0, h->d_EM, nullptr, h->d_fin,
+                                     h->stream));
     int64_t em[2];
     ISING_HIP(hipMemcpyAsync(em, h->d_EM, sizeof em, hipMemcpyDeviceToHost, h->stream));
     ISING_HIP(hipStreamSynchronize(h->stream));
@@ -318,10 +378,11 @@ int ising_autotune(ising_lattice* h, double T, double* best_ms_per_sweep) {
     const int blocks[3] = {64, 128, 256};
     for (int wi = 0; wi < 3 && rc == ISING_OK; ++wi) {
         for (int bi = 0; bi < 3 && rc == ISING_OK; ++bi) {
-            rc = enqueue_sweeps(h, scratch, h->t, T, 1, 0, nullptr, nullptr, wpts[wi], blocks[bi]);  // warm-up
+            rc = enqueue_sweeps(h, scratch, h->t, T, 1, 0, nullptr, nullptr, nullptr, wpts[wi], blocks[bi]);  // warm-up
             if (rc != ISING_OK) break;
             e = hipEventRecord(e0, h->stream);
-            if (e == hipSuccess) rc = enqueue_sweeps(h, scratch, h->t, T, n_time, 0, nullptr, nullptr, wpts[wi], blocks[bi]);
+            if (e == hipSuccess)
+                rc = enqueue_sweeps(h, scratch, h->t, T, n_time, 0, nullptr, nullptr, nullptr, wpts[wi], blocks[bi]);
             if (rc != ISING_OK) break;
             if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);

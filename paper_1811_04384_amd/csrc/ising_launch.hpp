@@ -27,13 +27,15 @@ hipError_t launch_halfsweep_single(int wpt, int block, uint64_t* W, const SweepA
 int64_t halfsweep_single_waves(const Geometry& g, int wpt, int block);
 
 // Sum the partials of one lattice into E, M and store them: sample index
-// `idx` of series (if non-null), and out_EM[0..1] (if non-null).  `scratch`
+// `idx` of series (if non-null), out_EM[0..1] (if non-null), and add them to
+// the moment sums `mom` (if non-null, device memory).  `scratch`
 // is finalize_scratch_bytes() of device memory, zeroed once before first use
 // (the kernel leaves it ready for the next call); calls sharing a scratch
 // buffer must be ordered on one stream.
 size_t finalize_scratch_bytes();
 hipError_t launch_finalize_single(const Partial* partials, int64_t n_partials, int32_t L, int64_t* series_E,
-                                  int64_t* series_M, int64_t idx, int64_t* out_EM, void* scratch, hipStream_t s);
+                                  int64_t* series_M, int64_t idx, int64_t* out_EM, Moments* mom, void* scratch,
+                                  hipStream_t s);
 
 // Observables of one lattice: per-wavefront partials of right+down
 // antiparallel bonds and up spins over all words.

@@ -63,3 +63,49 @@ def test_invalid_sizes_fail_before_touching_a_gpu():
         ising.ising_batch_create([64, 63], [1, 2], [1, 1], stream=0)
     with pytest.raises(ising.IsingError):
         ising.ising_server_create(1 << 20, 0, 10, stream=0)
+
+
+def test_thermodynamics_host_equals_oracle():
+    """The library's host-side derivation of e, c, |m|, chi and the Binder
+    cumulant from exact moment sums agrees with the oracle's exact rational
+    evaluation, including sums that need every 64-bit limb."""
+    import random
+
+    rng = random.Random(7)
+    cases = []
+    for L in (4, 64, 4096, 32768, 1 << 18):
+        N = L * L
+        for _ in range(6):
+            n = rng.randint(1, 5000)
+            Es = [-rng.randint(N // 2, 2 * N) for _ in range(min(n, 50))]
+            Ms = [rng.randint(-N, N) for _ in range(min(n, 50))]
+            reps = n // len(Es) or 1
+            m = oracle.moments(Es * reps, Ms * reps)
+            cases.append((m, L, rng.uniform(0.5, 6.0)))
+    for m, L, T in cases:
+        got = ising.ising_thermodynamics(m, L, T)
+        want = oracle.thermodynamics(m, L, T)
+        for k in ("e", "abs_m", "binder"):
+            assert got[k] == pytest.approx(want[k], rel=1e-12, abs=1e-15), (k, L)
+        for k in ("c", "chi"):  # differences of near-equal means: relative to the larger term
+            scale = max(abs(want[k]), 1e-6 * (4.0 if k == "c" else 1.0) * L * L / T)
+            assert abs(got[k] - want[k]) <= 1e-9 * scale, (k, L, got[k], want[k])
+    assert m["sum_M4"] >= 1 << 128  # the third limb was exercised
+
+
+def test_moment_calls_reject_bad_arguments_without_a_gpu():
+    zero = {"n_samples": 0, "sum_E": 0, "sum_E2": 0, "sum_absM": 0, "sum_M2": 0, "sum_M4": 0}
+    one = dict(zero, n_samples=1, sum_E=-32, sum_E2=1024, sum_absM=16, sum_M2=256, sum_M4=65536)
+    with pytest.raises(ising.IsingError) as e:
+        ising.ising_thermodynamics(zero, 4, 2.0)
+    assert e.value.code == ising.ISING_EINVAL
+    for L, T in ((5, 2.0), (4, 0.0), (4, float("nan")), (0, 2.0)):
+        with pytest.raises(ising.IsingError):
+            ising.ising_thermodynamics(one, L, T)
+    assert ising.ising_thermodynamics(one, 4, 2.0) == {"e": -2.0, "c": 0.0, "abs_m": 1.0, "chi": 0.0,
+                                                        "binder": 2.0 / 3.0}
+    lib = ising.load()
+    assert lib.ising_scan(None, 1, None, 0, 1, 1, None) == ising.ISING_EINVAL
+    assert lib.ising_batch_scan(None, 1, None, 0, 1, 1, None) == ising.ISING_EINVAL
+    assert lib.ising_sweep_moments(None, 2.0, 1, 1, None) == ising.ISING_EINVAL
+    assert lib.ising_batch_moments(None, None) == ising.ISING_EINVAL
