@@ -12,8 +12,10 @@ Printed: ONE JSON line with the contract fields, a `roofline` object for the
 dominant kernel (the half-sweep kernel, integer-ALU bound), a `cpu_baseline`
 object (the CPU oracle on a bounded sample of the same workload) and a
 `secondary` object with the other workloads: the plain one-lattice-per-launch
-L = 4096 run, the batched mixed-L run, the L = 64 temperature scan and a
-served request stream with p50/p99 latency.
+L = 4096 run, the batched mixed-L run, the L = 64 temperature scan, heating
+scans of L = 1008 replicas with the lattice carried over (energy and specific
+heat per temperature), the paper's own 101-temperature scan of its L = 84
+lattice, and a served request stream with p50/p99 latency.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -297,6 +299,57 @@ def run_scan64(ising, therm=2000, meas=2000):
             "unit": UNIT, "mean_e_per_spin": mean_e, "mean_absm_per_spin": mean_m}
 
 
+def run_heating_scan(ising, L=1008, replicas=16, therm=500, meas=1000):
+    """Heating scans with the lattice carried over from one temperature to
+    the next: 16 replicas of the L = 1008 (N = 48) lattice, ordered (cold)
+    start, seeds 0..15, T = 1.5, 1.6, ..., 3.5, at each T 500 sweeps to
+    re-equilibrate and
+    1000 sweeps sampled after each one, exact moment sums on the device.
+    Reports the whole-scan throughput and the replica-averaged e(T), c(T)."""
+    import torch
+
+    Ts = [round(1.5 + 0.1 * j, 10) for j in range(21)]
+    b = ising.Batch([L] * replicas, list(range(replicas)), hot=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = b.scan(Ts, therm, meas, 1)
+    wall = time.perf_counter() - t0
+    plan = b.plan()
+    b.close()
+    e_T, c_T = [], []
+    for j, T in enumerate(Ts):
+        th = [ising.ising_thermodynamics(out[j][r], L, T) for r in range(replicas)]
+        e_T.append(round(sum(x["e"] for x in th) / replicas, 5))
+        c_T.append(round(sum(x["c"] for x in th) / replicas, 4))
+    att = replicas * L * L * len(Ts) * (therm + meas)
+    return {"workload": f"{replicas} x L={L} (N=48) cold, heating T=1.5..3.5 step 0.1, {therm}+{meas} sweeps per T",
+            "value": round(att / (wall * 1e9), 3), "unit": UNIT, "wall_s": round(wall, 3), "plan": plan,
+            "T": Ts, "mean_e_per_spin": e_T, "c_per_spin": c_T, "c_peak_T": Ts[max(range(len(Ts)), key=c_T.__getitem__)]}
+
+
+def run_paper_scan(ising, L=84, replicas=8, iterations=400, per_iteration=10):
+    """The paper's own temperature loop on its demonstration lattice (N = 4,
+    L = 84): random start, T = 0.001, 0.101, ..., 10.001 with the lattice
+    carried over, at each T 400 iterations of 10 updates per spin (10 sweeps),
+    the energy recorded after every iteration and all iterations averaged.
+    Eight replicas (seeds 0..7) in one batch."""
+    import torch
+
+    Ts = [0.001 + 0.1 * k for k in range(101)]
+    b = ising.Batch([L] * replicas, list(range(replicas)), hot=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = b.scan(Ts, 0, iterations * per_iteration, per_iteration)
+    wall = time.perf_counter() - t0
+    b.close()
+    e_T = [sum(out[j][r]["sum_E"] for r in range(replicas)) / (replicas * iterations * L * L) for j in range(len(Ts))]
+    att = replicas * L * L * len(Ts) * iterations * per_iteration
+    return {"workload": f"{replicas} x L={L} (N=4) hot, T=0.001..10.001 step 0.1 carried over, "
+                        f"{iterations} iterations x {per_iteration} sweeps, E after each iteration",
+            "value": round(att / (wall * 1e9), 3), "unit": UNIT, "wall_s": round(wall, 3),
+            "T_every_5th": [round(T, 3) for T in Ts[::5]], "mean_e_per_spin_every_5th": [round(e, 4) for e in e_T[::5]]}
+
+
 def run_serving(ising, rate=25.0, duration=10.0, quantum=100, seed=2026):
     """Poisson request stream: L = 2^U{7..12}, T ~ U[1.5, 3.5], sweeps ~
     U{1000..20000}, hot start with seed = request id; continuous batching."""
@@ -355,7 +408,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sweeps", type=int, default=SWEEPS_MAIN, help="sweeps per temperature (headline: 2000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--secondary", default="plain4096,graph4096,batched,scan64,serving",
+    ap.add_argument("--secondary", default="plain4096,graph4096,batched,scan64,heating_scan,paper_scan,serving",
                     help="comma list of secondary workloads, or 'none'")
     ap.add_argument("--serving-rate", type=float, default=25.0)
     ap.add_argument("--serving-duration", type=float, default=10.0)
@@ -414,6 +467,10 @@ def main():
             secondary[name] = run_batched(ising)
         elif name == "scan64":
             secondary[name] = run_scan64(ising)
+        elif name == "heating_scan":
+            secondary[name] = run_heating_scan(ising)
+        elif name == "paper_scan":
+            secondary[name] = run_paper_scan(ising)
         elif name == "serving":
             secondary[name] = run_serving(ising, args.serving_rate, args.serving_duration, args.serving_quantum)
         log(f"  {secondary.get(name)}")

@@ -124,3 +124,28 @@ def test_gpu_heating_scan_specific_heat_matches_kaufman():
             vals = np.array([x[key] for x in th])
             err = vals.std(ddof=1) / math.sqrt(R)
             assert abs(vals.mean() - exact) < 5 * err + 1e-3 * abs(exact), (T, key, vals.mean(), exact, err)
+
+
+def test_paper_scan_energy_matches_kaufman():
+    """The paper's driver loop on its demonstration lattice (N = 4, L = 84):
+    T = 0.001, 0.101, ..., 10.001 with the lattice carried over, at each T
+    400 iterations of 10 updates per spin with the energy recorded after each
+    iteration and every iteration averaged (nothing discarded).  Eight
+    replicas from a cold start; the replica-mean energy per spin at each of
+    the 101 temperatures against Kaufman's exact value for the 84 x 84 torus.
+    Near T_c the 4000-sweep averages carry a larger error, which the spread
+    over replicas measures."""
+    L, R = 84, 8
+    Ts = [0.001 + 0.1 * k for k in range(101)]
+    b = ising.Batch([L] * R, list(range(R)), hot=False)
+    out = b.scan(Ts, 0, 4000, 10)
+    b.close()
+    worst = 0.0
+    for j, T in enumerate(Ts):
+        assert all(out[j][r]["n_samples"] == 400 for r in range(R))
+        e = np.array([out[j][r]["sum_E"] / 400 / L ** 2 for r in range(R)])
+        err = e.std(ddof=1) / math.sqrt(R)
+        exact = kaufman_energy(L, T)
+        assert abs(e.mean() - exact) < 5 * err + 2e-3, (T, e.mean(), exact, err)
+        worst = max(worst, abs(e.mean() - exact))
+    print(f"largest |e - e_exact| over 101 temperatures: {worst:.2e}", flush=True)
