@@ -55,6 +55,17 @@ def _load():
     lib.oracle_init_window.restype = ctypes.c_int
     lib.oracle_sweep_window.argtypes = [i32, u64, u64, i64, dbl, i32, i32, i32, i32, u8p, i32]
     lib.oracle_sweep_window.restype = ctypes.c_int
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.oracle_picks_per_phase.argtypes = [i32, i32, i32]
+    lib.oracle_picks_per_phase.restype = i64
+    lib.oracle_pick.argtypes = [u64, u64, i32, i32, i32, i32, u32, i32p, i32p]
+    lib.oracle_pick.restype = None
+    lib.oracle_pick_uniform.argtypes = [u64, u64, i32, i32, u32, i32]
+    lib.oracle_pick_uniform.restype = u32
+    lib.oracle_random_valid.argtypes = [i32, i32]
+    lib.oracle_random_valid.restype = ctypes.c_int
+    lib.oracle_random_iterations.argtypes = [i32, u64, u64, i64, dbl, i32, u8p, i32, i64p, i64p, i32, i32]
+    lib.oracle_random_iterations.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -212,3 +223,43 @@ def sweep_window(win, L, seed, t0, n_sweeps, T, r0, c0, threads=0):
                                      int(h), int(w), _u8(win), int(threads))
     if rc != 0:
         raise ValueError("bad window sweep")
+
+
+def picks_per_phase(L, S, phase):
+    """Words a strip of S columns updates in one phase: 10 N floor(S/2) for
+    phase 0, 10 N (S - floor(S/2)) for phase 1."""
+    return int(_load().oracle_picks_per_phase(int(L), int(S), int(phase)))
+
+
+def pick(seed, t, L, S, phase, p, k):
+    """(word row I, word column J) of pick k of strip p in a phase of iteration t."""
+    I, J = ctypes.c_int32(), ctypes.c_int32()
+    _load().oracle_pick(int(seed), int(t), int(L), int(S), int(phase), int(p), int(k), ctypes.byref(I),
+                        ctypes.byref(J))
+    return int(I.value), int(J.value)
+
+
+def pick_uniform(seed, t, phase, p, k, q):
+    return int(_load().oracle_pick_uniform(int(seed), int(t), int(phase), int(p), int(k), int(q)))
+
+
+def random_valid(L, S):
+    return bool(_load().oracle_random_valid(int(L), int(S)))
+
+
+def random_iterations(s, seed, t0, n_iter, T, S, every=0, order=0, threads=0):
+    """The paper's strip dynamics (random word picks, two phases per
+    iteration) on state ``s`` in place, starting at absolute iteration t0.
+    With every > 0 returns (E_series, M_series) sampled after every
+    every-th iteration of this call."""
+    assert s.dtype == np.uint8 and s.flags.c_contiguous and s.shape[0] == s.shape[1]
+    L = s.shape[0]
+    n = int(n_iter)
+    k = n // every if every > 0 else 0
+    Es = np.zeros(max(k, 1), dtype=np.int64)
+    Ms = np.zeros(max(k, 1), dtype=np.int64)
+    rc = _load().oracle_random_iterations(L, int(seed), int(t0), n, float(T), int(S), _u8(s), int(every),
+                                          _i64(Es), _i64(Ms), int(order), int(threads))
+    if rc != 0:
+        raise ValueError("bad strip-dynamics arguments")
+    return (Es[:k], Ms[:k]) if every > 0 else None

@@ -320,3 +320,135 @@ ORACLE_API int oracle_sweep_window(int32_t L, uint64_t seed, uint64_t t0, int64_
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The paper's own dynamics: random word selection inside strips, two       */
+/* phases per iteration (Sections 4 and 5.2, Table 2).                      */
+/*                                                                           */
+/* The word lattice (N word rows x L columns) is cut into L / S vertical     */
+/* strips of S word columns; strip p owns columns [pS, pS + S) (one          */
+/* process's sub-lattice, Section 4).  One iteration is two phases.  In      */
+/* phase 0 every strip updates 10 N h0 words of its left h0 = floor(S/2)     */
+/* columns, in phase 1 10 N h1 words of its right h1 = S - h0 columns, each  */
+/* word chosen uniformly at random with replacement (ten updates per word on */
+/* average, Table 2).  A strip's picks are applied one after another, each   */
+/* to the current state.  The columns a strip updates in a phase border only */
+/* columns that no strip updates in that phase (Section 4: the border words  */
+/* of neighbouring processes are never updated at the same time), so strips  */
+/* are independent inside a phase and their order does not matter.          */
+/*                                                                           */
+/* Updating a word applies the Metropolis rule to each of its live spins     */
+/* given the current neighbours.  The spins of one word (rows I + qN) never  */
+/* neighbour each other for even N >= 2, so visiting them one by one equals  */
+/* the simultaneous word update of Section 3.1.                              */
+/*                                                                           */
+/* Reproducible random numbers replace the paper's reseeded generator; with */
+/* h the phase, t the iteration and key = seed:                              */
+/*   pick k of strip p:  counter (t mod 2^32, p, k div 2,                    */
+/*                                8 (2 + h) + 256 (t div 2^32))              */
+/*     -> (x, y, z, w); pick k uses (x, y) for even k, (z, w) for odd k:     */
+/*     word row I = floor(x N / 2^32) and column                             */
+/*     J = pS + o_h + floor(y w_h / 2^32), with o_0 = 0, o_1 = h0 and w_h    */
+/*     the phase's width;                                                    */
+/*   uniform of position q (0..20) in pick k:  counter (t mod 2^32, p, k,    */
+/*     g + 8 (4 + h) + 256 (t div 2^32)), g = q div 4, output q mod 4 (for   */
+/*     q = 20: g = 5, output 0).                                             */
+/* ------------------------------------------------------------------------ */
+#define PICK_LIMIT (1u << 22) /* picks of one strip in one phase */
+
+static int32_t phase_width(int32_t S, int32_t h) { return h == 0 ? S / 2 : S - S / 2; }
+
+ORACLE_API int64_t oracle_picks_per_phase(int32_t L, int32_t S, int32_t h)
+{
+    return 10 * (int64_t)oracle_word_rows(L) * phase_width(S, h);
+}
+
+ORACLE_API void oracle_pick(uint64_t seed, uint64_t t, int32_t L, int32_t S, int32_t h, int32_t p,
+                            uint32_t k, int32_t* I, int32_t* J)
+{
+    uint32_t ctr[4], key[2], out[4];
+    ctr[0] = (uint32_t)t;
+    ctr[1] = (uint32_t)p;
+    ctr[2] = k >> 1;
+    ctr[3] = 8u * (uint32_t)(2 + h) + ((uint32_t)(t >> 32) << 8);
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    oracle_philox4x32_10(ctr, key, out);
+    uint32_t x = (k & 1) ? out[2] : out[0];
+    uint32_t y = (k & 1) ? out[3] : out[1];
+    int32_t N = oracle_word_rows(L);
+    *I = (int32_t)(((uint64_t)x * (uint64_t)N) >> 32);
+    *J = p * S + (h == 0 ? 0 : S / 2) + (int32_t)(((uint64_t)y * (uint64_t)phase_width(S, h)) >> 32);
+}
+
+ORACLE_API uint32_t oracle_pick_uniform(uint64_t seed, uint64_t t, int32_t h, int32_t p, uint32_t k,
+                                        int32_t q)
+{
+    uint32_t g = q < 20 ? (uint32_t)(q >> 2) : 5u;
+    uint32_t ctr[4], key[2], out[4];
+    ctr[0] = (uint32_t)t;
+    ctr[1] = (uint32_t)p;
+    ctr[2] = k;
+    ctr[3] = g + 8u * (uint32_t)(4 + h) + ((uint32_t)(t >> 32) << 8);
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    oracle_philox4x32_10(ctr, key, out);
+    return q < 20 ? out[q & 3] : out[0];
+}
+
+static void strip_phase(int32_t L, int32_t S, uint64_t seed, uint64_t t, int32_t h, int32_t p,
+                        uint32_t t4, uint32_t t8, uint8_t* s)
+{
+    int32_t N = oracle_word_rows(L);
+    int64_t picks = oracle_picks_per_phase(L, S, h);
+    for (int64_t k = 0; k < picks; ++k) {
+        int32_t I, J;
+        oracle_pick(seed, t, L, S, h, p, (uint32_t)k, &I, &J);
+        for (int32_t q = 0; q < 21; ++q) {
+            int32_t r = I + q * N;
+            if (r >= L) break; /* dead slot */
+            int n = count_anti(L, s, r, J);
+            uint32_t u = oracle_pick_uniform(seed, t, h, p, (uint32_t)k, q);
+            if (oracle_accept(n, u, t4, t8)) s[(int64_t)r * L + J] ^= 1u;
+        }
+    }
+}
+
+ORACLE_API int oracle_random_valid(int32_t L, int32_t S)
+{
+    if (!valid_L(L) || S < 2 || S > L || L % S != 0) return 0;
+    return oracle_picks_per_phase(L, S, 1) <= (int64_t)PICK_LIMIT;
+}
+
+/*
+ * n_iter iterations of the strip dynamics at temperature T starting at the
+ * absolute iteration index t0; after iteration k (1-based in this call) with
+ * k % every == 0 the observables go to E_series[k/every - 1], M_series[...].
+ * order 0: strips in parallel (OpenMP), 1: strips one by one, last first.
+ * Returns 0, or -1 on bad arguments.
+ */
+ORACLE_API int oracle_random_iterations(int32_t L, uint64_t seed, uint64_t t0, int64_t n_iter, double T,
+                                        int32_t S, uint8_t* s, int32_t every, int64_t* E_series,
+                                        int64_t* M_series, int32_t order, int32_t nthreads)
+{
+    if (!oracle_random_valid(L, S) || n_iter < 0 || !(T > 0.0) || isinf(T)) return -1;
+    if ((t0 + (uint64_t)n_iter) >> 56) return -1;
+    set_threads(nthreads);
+    uint32_t t4, t8;
+    oracle_thresholds(T, &t4, &t8);
+    const int32_t P = L / S;
+    for (int64_t k = 1; k <= n_iter; ++k) {
+        uint64_t t = t0 + (uint64_t)(k - 1);
+        for (int32_t h = 0; h < 2; ++h) {
+            if (order == 0) {
+#pragma omp parallel for schedule(dynamic, 1)
+                for (int32_t p = 0; p < P; ++p) strip_phase(L, S, seed, t, h, p, t4, t8, s);
+            } else {
+                for (int32_t p = P - 1; p >= 0; --p) strip_phase(L, S, seed, t, h, p, t4, t8, s);
+            }
+        }
+        if (every > 0 && E_series && M_series && k % every == 0)
+            oracle_observables(L, s, &E_series[k / every - 1], &M_series[k / every - 1]);
+    }
+    return 0;
+}
