@@ -181,6 +181,33 @@ int ising_sweep_moments(ising_lattice* h, double T, int64_t n_sweeps, int32_t ev
 int ising_scan(ising_lattice* h, int32_t n_T, const double* T, int64_t therm, int64_t meas, int32_t every,
                ising_moments* out);
 
+/* The paper's own dynamics instead of the checkerboard: random word
+   selection inside vertical strips (Sections 4 and 5.2).  The word lattice
+   is cut into L/strip_cols strips of strip_cols word columns (one process's
+   sub-lattice each; 2 <= strip_cols <= L, strip_cols divides L).  One
+   iteration is two phases: in phase 0 every strip updates
+   10 N floor(strip_cols/2) words of its left floor(strip_cols/2) columns,
+   in phase 1 10 N (strip_cols - floor(strip_cols/2)) words of its right
+   columns, each word chosen uniformly with replacement and updated from the
+   current state (ten updates per word on average, Table 2).  Strips are
+   independent inside a phase (their border words are never updated in the
+   same phase, Section 4) and run in parallel.  Random numbers, with h the
+   phase, t the absolute iteration index (the handle's sweep counter) and
+   key = seed: pick k of strip p uses Philox counter
+   (t mod 2^32, p, k div 2, 8 (2 + h) + 256 (t div 2^32)), outputs (x, y) for
+   even k and (z, w) for odd k, word row floor(x N / 2^32) and column
+   p strip_cols + (h ? floor(strip_cols/2) : 0) + floor(y width / 2^32); the
+   uniform of position q of pick k is output q mod 4 (q = 20: output 0) of
+   counter (t mod 2^32, p, k, g + 8 (4 + h) + 256 (t div 2^32)),
+   g = min(q div 4, 5).  Acceptance as for the checkerboard.
+   After the k-th iteration of this call with k % every == 0, E and M are
+   stored at dev_E[k/every - 1], dev_M[k/every - 1] and added to *dev_acc
+   (device pointers; each may be NULL; every >= 1 when any is given,
+   every = 0 takes no samples).  Advances the sweep counter by n_iterations.
+   EINVAL if a strip would apply more than 2^22 picks in one phase. */
+int ising_random_iterations(ising_lattice* h, double T, int32_t strip_cols, int64_t n_iterations, int32_t every,
+                            int64_t* dev_E, int64_t* dev_M, ising_moments* dev_acc);
+
 /* E and M of the current state (host pointers).  Synchronises the stream. */
 int ising_observables(ising_lattice* h, int64_t* E, int64_t* M);
 

@@ -162,6 +162,11 @@ def ising_thermodynamics(m, L, T):
     return out.as_dict()
 
 
+def ising_random_iterations(h, T, strip_cols, n_iterations, every=0, dev_E=None, dev_M=None, dev_acc=None):
+    _check(_lib.load().ising_random_iterations(h, float(T), int(strip_cols), int(n_iterations), int(every),
+                                               _ptr(dev_E), _ptr(dev_M), _ptr(dev_acc)))
+
+
 def ising_observables(h):
     E, M = ctypes.c_int64(), ctypes.c_int64()
     _check(_lib.load().ising_observables(h, ctypes.byref(E), ctypes.byref(M)))
@@ -384,6 +389,20 @@ class Lattice:
 
     def scan(self, T, therm, meas, every=1):
         return ising_scan(self.handle, T, therm, meas, every)
+
+    def random_iterations(self, T, strip_cols, n, every=0, acc=None):
+        """The paper's strip dynamics; with every > 0 returns device (E, M)
+        series of n // every samples (and adds them to `acc` if given)."""
+        import torch
+
+        if every > 0:
+            k = int(n) // int(every)
+            E = torch.empty(max(k, 1), dtype=torch.int64, device=self.words.device)
+            M = torch.empty(max(k, 1), dtype=torch.int64, device=self.words.device)
+            ising_random_iterations(self.handle, T, strip_cols, n, every, E, M, acc)
+            return E[:k], M[:k]
+        ising_random_iterations(self.handle, T, strip_cols, n, 0)
+        return None
 
     def observables(self):
         return ising_observables(self.handle)

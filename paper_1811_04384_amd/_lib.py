@@ -61,6 +61,7 @@ SIGNATURES = {
     "ising_sweep_moments": (c_int, [c_vp, c_dbl, c_i64, c_i32, c_vp]),
     "ising_scan": (c_int, [c_vp, c_i32, P(c_dbl), c_i64, c_i64, c_i32, P(Moments)]),
     "ising_thermodynamics": (c_int, [P(Moments), c_i32, c_dbl, P(Thermo)]),
+    "ising_random_iterations": (c_int, [c_vp, c_dbl, c_i32, c_i64, c_i32, c_vp, c_vp, c_vp]),
     "ising_observables": (c_int, [c_vp, P(c_i64), P(c_i64)]),
     "ising_get_spins": (c_int, [c_vp, c_vp]),
     "ising_get_spins_region": (c_int, [c_vp, c_i32, c_i32, c_i32, c_i32, c_vp]),

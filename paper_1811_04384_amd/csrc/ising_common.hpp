@@ -36,6 +36,19 @@ struct SweepArgs {
     uint32_t t4, t8;      // acceptance thresholds
 };
 
+// One phase of the strip dynamics (random word picks inside vertical strips
+// of S word columns): every strip applies `picks` picks, in order, to the
+// `width` columns starting at its column `off`.
+struct StripArgs {
+    int32_t L, N, istar, sh_star;
+    int32_t S, off, width, strips;
+    uint32_t picks;       // picks per strip in this phase
+    uint32_t phase;       // 0: left half, 1: right half
+    uint32_t t_lo, t_hi;  // absolute iteration index
+    uint32_t k0, k1;      // Philox key = seed
+    uint32_t t4, t8;      // acceptance thresholds
+};
+
 // Per-lattice parameters of a batch, written by the host before each call
 // and read-only for every kernel.
 struct LatticeDesc {

@@ -165,6 +165,54 @@ __device__ __forceinline__ void energy_magnetisation(uint64_t anti, uint64_t ups
     M = 2 * (int64_t)ups - n;
 }
 
+// ---------------------------------------------------------------------------
+// Strip dynamics (random word picks, two phases per iteration): one thread
+// per strip applies that strip's picks of one phase in order.  Strips never
+// touch each other's words inside a phase, so threads need no
+// synchronisation; a thread sees its own earlier stores.  Pick k draws its
+// word from Philox counter (t lo, strip, k div 2, 8 (2 + phase) + 256 t hi)
+// -- outputs (x, y) for even k, (z, w) for odd k; row floor(x N / 2^32),
+// column off + floor(y width / 2^32) -- and its 21 uniforms from counters
+// (t lo, strip, k, g + 8 (4 + phase) + 256 t hi), g = 0..5.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_strip_phase(uint64_t* __restrict__ W, StripArgs a) {
+    const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= a.strips) return;
+    const int L = a.L, N = a.N;
+    auto ld = [&](int i, int j) { return W[(size_t)i * (size_t)L + (size_t)j]; };
+    const uint32_t c3_pick = 8u * (2u + a.phase) + (a.t_hi << 8);
+    const uint32_t c3_word = 8u * (4u + a.phase) + (a.t_hi << 8);
+    const int col0 = p * a.S + a.off;
+    U4 pick = {0u, 0u, 0u, 0u};
+    for (uint32_t k = 0; k < a.picks; ++k) {
+        if ((k & 1u) == 0u) pick = philox_lane_c1(a.t_lo, (uint32_t)p, k >> 1, c3_pick, a.k0, a.k1);
+        const uint32_t x = (k & 1u) ? pick.z : pick.x;
+        const uint32_t y = (k & 1u) ? pick.w : pick.y;
+        const int I = (int)(((uint64_t)x * (uint64_t)(uint32_t)N) >> 32);
+        const int J = col0 + (int)(((uint64_t)y * (uint64_t)(uint32_t)a.width) >> 32);
+        const uint64_t w = ld(I, J);
+        const uint64_t lf = ld(I, J == 0 ? L - 1 : J - 1);
+        const uint64_t rt = ld(I, J == L - 1 ? 0 : J + 1);
+        const uint64_t up = up_word(ld, I, J, N, a.istar, a.sh_star);
+        const uint64_t dn = down_word(ld, I, J, N, a.istar, a.sh_star);
+        // every position draws (dead slots are masked by `live`), so lanes
+        // with different rows run the same instructions
+        Codes codes = {0u, 0u, 0u};
+#pragma unroll
+        for (int g = 0; g < 5; ++g) {
+            const U4 r = philox_lane_c1(a.t_lo, (uint32_t)p, k, (uint32_t)g + c3_word, a.k0, a.k1);
+            append_draw(codes, 4 * g + 0, r.x, a.t4, a.t8);
+            append_draw(codes, 4 * g + 1, r.y, a.t4, a.t8);
+            append_draw(codes, 4 * g + 2, r.z, a.t4, a.t8);
+            append_draw(codes, 4 * g + 3, r.w, a.t4, a.t8);
+        }
+        const U4 r5 = philox_lane_c1(a.t_lo, (uint32_t)p, k, 5u + c3_word, a.k0, a.k1);
+        append_draw(codes, 20, r5.x, a.t4, a.t8);
+        const uint64_t f = flip_mask(w, up, dn, lf, rt, assemble_codes(codes), live_mask(I, L, N));
+        W[(size_t)I * (size_t)L + (size_t)J] = w ^ f;
+    }
+}
+
 // Adds the sample (E, M) to exact moment sums.  For L <= 2^18, |E| <= 2 L^2
 // <= 2^37 and |M| <= L^2 = 2^36, so E^2 and M^2 fit 128 bits; M^4 < 2^144 is
 // formed in three limbs from q = M^2 = qh 2^64 + ql (qh < 2^8):
@@ -516,6 +564,12 @@ hipError_t launch_finalize_single(const Partial* partials, int64_t n_partials, i
                                                            2 * kFinalizeBlocks * sizeof(unsigned long long));
     hipLaunchKernelGGL(k_finalize_single, dim3(blocks), dim3(256), 0, s, partials, n_partials, L, series_E, series_M,
                        idx, out_EM, mom, sums, ticket);
+    return hipGetLastError();
+}
+
+hipError_t launch_strip_phase(uint64_t* W, const StripArgs& a, hipStream_t s) {
+    if (a.strips <= 0 || a.picks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_strip_phase, dim3(grid_for((uint64_t)a.strips, 64)), dim3(64), 0, s, W, a);
     return hipGetLastError();
 }
 

@@ -244,6 +244,62 @@ int ising_scan(ising_lattice* h, int32_t n_T, const double* T, int64_t therm, in
     return rc;
 }
 
+// Largest number of picks one strip may apply in one phase (bounds the run
+// time of one thread).
+constexpr int64_t kStripPickLimit = int64_t(1) << 22;
+
+int ising_random_iterations(ising_lattice* h, double T, int32_t strip_cols, int64_t n_iterations, int32_t every,
+                            int64_t* dev_E, int64_t* dev_M, ising_moments* dev_acc) {
+    if (!h) return fail(ISING_EINVAL, "ising_random_iterations: null handle");
+    if (!valid_T(T)) return fail(ISING_EINVAL, "ising_random_iterations: T must be finite and > 0 (got %g)", T);
+    const int32_t L = h->g.L, N = h->g.N;
+    if (strip_cols < 2 || strip_cols > L || L % strip_cols != 0)
+        return fail(ISING_EINVAL, "ising_random_iterations: strip_cols %d must be >= 2 and divide L = %d",
+                    strip_cols, L);
+    const int64_t picks1 = 10 * (int64_t)N * (strip_cols - strip_cols / 2);
+    if (picks1 > kStripPickLimit)
+        return fail(ISING_EINVAL, "ising_random_iterations: %lld picks per strip and phase exceed %lld",
+                    (long long)picks1, (long long)kStripPickLimit);
+    if (n_iterations < 0 || every < 0) return fail(ISING_EINVAL, "ising_random_iterations: negative count");
+    if ((dev_E || dev_M || dev_acc) && every == 0)
+        return fail(ISING_EINVAL, "ising_random_iterations: outputs need every >= 1");
+    if ((h->t + (uint64_t)n_iterations) >> 56)
+        return fail(ISING_EINVAL, "ising_random_iterations: iteration index beyond 2^56");
+    uint32_t t4, t8;
+    thresholds_of(T, &t4, &t8);
+    StripArgs a;
+    a.L = L;
+    a.N = N;
+    a.istar = h->g.istar;
+    a.sh_star = h->g.sh_star;
+    a.S = strip_cols;
+    a.strips = L / strip_cols;
+    a.k0 = (uint32_t)h->seed;
+    a.k1 = (uint32_t)(h->seed >> 32);
+    a.t4 = t4;
+    a.t8 = t8;
+    for (int64_t k = 1; k <= n_iterations; ++k) {
+        const uint64_t t = h->t + (uint64_t)(k - 1);
+        a.t_lo = (uint32_t)t;
+        a.t_hi = (uint32_t)(t >> 32);
+        for (uint32_t ph = 0; ph < 2; ++ph) {
+            a.phase = ph;
+            a.off = ph == 0 ? 0 : strip_cols / 2;
+            a.width = ph == 0 ? strip_cols / 2 : strip_cols - strip_cols / 2;
+            a.picks = (uint32_t)(10 * (int64_t)N * a.width);
+            ISING_HIP(launch_strip_phase(h->W, a, h->stream));
+        }
+        if (every > 0 && k % every == 0) {
+            int64_t nw = 0;
+            ISING_HIP(launch_observe_single(h->W, h->g, h->partials, &nw, h->stream));
+            ISING_HIP(launch_finalize_single(h->partials, nw, L, dev_E, dev_M, k / every - 1, nullptr,
+                                             reinterpret_cast<Moments*>(dev_acc), h->d_fin, h->stream));
+        }
+    }
+    h->t += (uint64_t)n_iterations;
+    return ISING_OK;
+}
+
 int ising_thermodynamics(const ising_moments* m, int32_t L, double T, ising_thermo* out) {
     if (!m || !out) return fail(ISING_EINVAL, "ising_thermodynamics: null argument");
     if (!valid_L(L)) return fail(ISING_EINVAL, "ising_thermodynamics: invalid L %d", L);

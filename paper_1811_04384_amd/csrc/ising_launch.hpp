@@ -37,6 +37,9 @@ hipError_t launch_finalize_single(const Partial* partials, int64_t n_partials, i
                                   int64_t* series_M, int64_t idx, int64_t* out_EM, Moments* mom, void* scratch,
                                   hipStream_t s);
 
+// One phase of the strip dynamics over all strips of one lattice.
+hipError_t launch_strip_phase(uint64_t* W, const StripArgs& a, hipStream_t s);
+
 // Observables of one lattice: per-wavefront partials of right+down
 // antiparallel bonds and up spins over all words.
 hipError_t launch_observe_single(const uint64_t* W, const Geometry& g, Partial* partials, int64_t* n_waves,
