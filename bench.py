@@ -15,7 +15,8 @@ object (the CPU oracle on a bounded sample of the same workload) and a
 L = 4096 run, the batched mixed-L run, the L = 64 temperature scan, heating
 scans of L = 1008 replicas with the lattice carried over (energy and specific
 heat per temperature), the paper's own 101-temperature scan of its L = 84
-lattice, and a served request stream with p50/p99 latency.
+lattice, the paper's three Table 2 cases run with its own random-pick strip
+dynamics, and a served request stream with p50/p99 latency.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -350,6 +351,38 @@ def run_paper_scan(ising, L=84, replicas=8, iterations=400, per_iteration=10):
             "T_every_5th": [round(T, 3) for T in Ts[::5]], "mean_e_per_spin_every_5th": [round(e, 4) for e in e_T[::5]]}
 
 
+def run_paper_cases(ising, strip_cols=2, T=2.269):
+    """The paper's three test cases (Table 2) with its own dynamics: random
+    word picks inside strips of `strip_cols` word columns (L / strip_cols
+    processes, each a GPU thread), left half then right half per iteration,
+    ten updates per word per iteration, the energy recorded after every
+    iteration.  Case 1: N = 96 (L = 2016), 5000 iterations; case 2: N = 96,
+    4500 iterations; case 3: N = 48 (L = 1008), 4500 iterations.  Hot start,
+    seed = case number, T = 2.269 (the paper gives no temperature for its
+    timing runs; the work per iteration does not depend on it)."""
+    import torch
+
+    out = {}
+    for case, (L, iters) in enumerate(((2016, 5000), (2016, 4500), (1008, 4500)), start=1):
+        lat = ising.Lattice(L, case, hot=True)
+        acc = torch.zeros(10, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        lat.random_iterations(T, strip_cols, iters, 1, acc)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        m = ising.moments_of(acc)
+        lat.close()
+        att = 10 * L * L * iters
+        out[f"case{case}"] = {"L": L, "N": L // 21, "iterations": iters, "processes": L // strip_cols,
+                              "value": round(att / (ms * 1e6), 3), "ms_per_iteration": round(ms / iters, 4),
+                              "mean_e_per_spin": round(m["sum_E"] / m["n_samples"] / L ** 2, 5)}
+    return {"workload": f"Table 2 cases, strip dynamics with {strip_cols}-column strips, T={T}", "unit": UNIT,
+            **out}
+
+
 def run_serving(ising, rate=25.0, duration=10.0, quantum=100, seed=2026):
     """Poisson request stream: L = 2^U{7..12}, T ~ U[1.5, 3.5], sweeps ~
     U{1000..20000}, hot start with seed = request id; continuous batching."""
@@ -408,7 +441,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sweeps", type=int, default=SWEEPS_MAIN, help="sweeps per temperature (headline: 2000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--secondary", default="plain4096,graph4096,batched,scan64,heating_scan,paper_scan,serving",
+    ap.add_argument("--secondary",
+                    default="plain4096,graph4096,batched,scan64,heating_scan,paper_scan,paper_cases,serving",
                     help="comma list of secondary workloads, or 'none'")
     ap.add_argument("--serving-rate", type=float, default=25.0)
     ap.add_argument("--serving-duration", type=float, default=10.0)
@@ -471,6 +505,8 @@ def main():
             secondary[name] = run_heating_scan(ising)
         elif name == "paper_scan":
             secondary[name] = run_paper_scan(ising)
+        elif name == "paper_cases":
+            secondary[name] = run_paper_cases(ising)
         elif name == "serving":
             secondary[name] = run_serving(ising, args.serving_rate, args.serving_duration, args.serving_quantum)
         log(f"  {secondary.get(name)}")

@@ -27,6 +27,8 @@ struct ising_lattice {
     int64_t partial_cap = 0;
     int64_t* d_EM = nullptr;  // device scratch: E, M of ising_observables
     void* d_fin = nullptr;    // device scratch of the partial-sum reduction
+    uint32_t* strip_pos = nullptr;    // drawn picks of the strip dynamics (allocated on first use)
+    uint64_t* strip_codes = nullptr;  // their acceptance codes
 };
 
 namespace ising {
@@ -71,6 +73,8 @@ static void release(ising_lattice* h) {
     if (h->partials) (void)hipFree(h->partials);
     if (h->d_EM) (void)hipFree(h->d_EM);
     if (h->d_fin) (void)hipFree(h->d_fin);
+    if (h->strip_pos) (void)hipFree(h->strip_pos);
+    if (h->strip_codes) (void)hipFree(h->strip_codes);
     delete h;
 }
 
@@ -247,6 +251,34 @@ int ising_scan(ising_lattice* h, int32_t n_T, const double* T, int64_t therm, in
 // Largest number of picks one strip may apply in one phase (bounds the run
 // time of one thread).
 constexpr int64_t kStripPickLimit = int64_t(1) << 22;
+// Picks drawn ahead per launch pair of the two-step strip path (all strips
+// together; 12 bytes each), and the largest LDS footprint of one strip for
+// which that path is used.
+constexpr int64_t kStripBufEntries = int64_t(1) << 22;
+constexpr size_t kStripChainLdsMax = 16 * 1024;
+
+static int strip_phase(ising_lattice* h, const StripArgs& a) {
+    if (strip_chain_lds_bytes(a) > kStripChainLdsMax) {
+        ISING_HIP(launch_strip_phase(h->W, a, h->stream));
+        return ISING_OK;
+    }
+    if (!h->strip_pos) {
+        ISING_HIP(hipMalloc(&h->strip_pos, sizeof(uint32_t) * kStripBufEntries));
+        hipError_t e = hipMalloc(&h->strip_codes, sizeof(uint64_t) * kStripBufEntries);
+        if (e != hipSuccess) {
+            (void)hipFree(h->strip_pos);
+            h->strip_pos = nullptr;
+            return hip_fail(e, "hipMalloc");
+        }
+    }
+    const uint32_t chunk = (uint32_t)std::max<int64_t>(1, kStripBufEntries / a.strips);
+    for (uint32_t k0 = 0; k0 < a.picks; k0 += chunk) {
+        const uint32_t n_k = std::min(chunk, a.picks - k0);
+        ISING_HIP(launch_strip_draws(a, k0, n_k, h->strip_pos, h->strip_codes, h->stream));
+        ISING_HIP(launch_strip_apply(h->W, a, n_k, h->strip_pos, h->strip_codes, h->stream));
+    }
+    return ISING_OK;
+}
 
 int ising_random_iterations(ising_lattice* h, double T, int32_t strip_cols, int64_t n_iterations, int32_t every,
                             int64_t* dev_E, int64_t* dev_M, ising_moments* dev_acc) {
@@ -287,7 +319,8 @@ int ising_random_iterations(ising_lattice* h, double T, int32_t strip_cols, int6
             a.off = ph == 0 ? 0 : strip_cols / 2;
             a.width = ph == 0 ? strip_cols / 2 : strip_cols - strip_cols / 2;
             a.picks = (uint32_t)(10 * (int64_t)N * a.width);
-            ISING_HIP(launch_strip_phase(h->W, a, h->stream));
+            const int rc = strip_phase(h, a);
+            if (rc != ISING_OK) return rc;
         }
         if (every > 0 && k % every == 0) {
             int64_t nw = 0;

@@ -37,8 +37,21 @@ hipError_t launch_finalize_single(const Partial* partials, int64_t n_partials, i
                                   int64_t* series_M, int64_t idx, int64_t* out_EM, Moments* mom, void* scratch,
                                   hipStream_t s);
 
-// One phase of the strip dynamics over all strips of one lattice.
+// One phase of the strip dynamics over all strips of one lattice, in one
+// kernel (each lane draws and applies its strip's picks).
 hipError_t launch_strip_phase(uint64_t* W, const StripArgs& a, hipStream_t s);
+
+// The same phase split in chunks of picks: launch_strip_draws computes the
+// words and acceptance codes of picks [k0, k0 + n_k) of every strip into
+// pos / codes (n_k * strips entries, pick-major), launch_strip_apply applies
+// them in order, the strip's columns held in LDS.  Usable when
+// strip_chain_lds_bytes(a) <= kStripLdsBytes.
+constexpr size_t kStripLdsBytes = 64 * 1024;
+size_t strip_chain_lds_bytes(const StripArgs& a);
+hipError_t launch_strip_draws(const StripArgs& a, uint32_t k0, uint32_t n_k, uint32_t* pos, uint64_t* codes,
+                              hipStream_t s);
+hipError_t launch_strip_apply(uint64_t* W, const StripArgs& a, uint32_t n_k, const uint32_t* pos,
+                              const uint64_t* codes, hipStream_t s);
 
 // Observables of one lattice: per-wavefront partials of right+down
 // antiparallel bonds and up spins over all words.

@@ -30,6 +30,9 @@ def _gpu():
     (130, 10, 4, True, 2.4, 3, 1),    # ragged word rows (dead slots)
     (2016, 28, 6, True, 2.269, 2, 1), # Table 2's N = 96 lattice on 72 processes
     (2016, 2, 7, True, 2.5, 1, 1),    # 1008 strips
+    (2016, 56, 8, True, 2.3, 1, 1),   # strip columns too large for LDS: one-kernel path
+    (1008, 1008, 9, False, 2.6, 1, 1),  # one strip of the whole lattice, one-kernel path
+    (5376, 2, 10, True, 2.4, 1, 1),   # 2688 strips: the picks of a phase are drawn in two chunks
 ])
 def test_strip_dynamics_matches_oracle(L, S, seed, hot, T, n, every):
     print(f"strips L={L} S={S} seed={seed}", flush=True)
