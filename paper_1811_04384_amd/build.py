@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libising.so")
 ARCH = "gfx950"
 
-SOURCES = [s for s in ["ising_kernels.hip", "ising_lattice.cpp", "ising_batch.cpp", "ising_server.cpp"]
+SOURCES = [s for s in ["ising_kernels.hip", "ising_strips.hip", "ising_lattice.cpp", "ising_batch.cpp", "ising_server.cpp"]
            if os.path.exists(os.path.join(CSRC, s))]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
