@@ -173,6 +173,8 @@ static int valid_L(int32_t L) { return L >= 4 && L <= (1 << 18) && (L % 2) == 0;
 ORACLE_API int oracle_init(int32_t L, uint64_t seed, int32_t hot, uint8_t* s)
 {
     if (!valid_L(L)) return -1;
+    /* every site's draw is independent of the others: rows in any order */
+#pragma omp parallel for schedule(static)
     for (int32_t r = 0; r < L; ++r)
         for (int32_t c = 0; c < L; ++c)
             s[(int64_t)r * L + c] = hot ? (uint8_t)(oracle_site_uniform(seed, 0, 0, L, r, c) < 0x80000000u)
@@ -224,10 +226,15 @@ ORACLE_API void oracle_observables(int32_t L, const uint8_t* s, int64_t* E, int6
     *M = m;
 }
 
+/* nthreads > 0 uses that many threads; 0 restores the count the process
+   started with (a call with an explicit count must not leak into later
+   calls). */
 static void set_threads(int32_t nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    static int initial = 0;
+    if (initial == 0) initial = omp_get_max_threads();
+    omp_set_num_threads(nthreads > 0 ? nthreads : initial);
 #else
     (void)nthreads;
 #endif

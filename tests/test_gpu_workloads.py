@@ -3,12 +3,18 @@
 - The L = 64 temperature scan: 8 lattices, cold start, seed 1234, 2000 + 2000
   sweeps with a sample after every measured sweep -- every sample of every
   lattice and the final states equal the oracle's (the whole run).
-- The 2048-lattice mixed batch in the benchmark's launch configuration: 64
-  sampled lattices (16 of each size) equal the oracle after the first 10
-  sweeps (with their E/M sample), and four L = 256 lattices stay equal over
-  500 sweeps.
+- The 2048-lattice mixed batch: the E/M samples of every one of the 2048
+  lattices after the first sweep and after 10 sweeps equal the oracle's, and
+  64 sampled lattices (16 of each size) equal it site by site after 10
+  sweeps, under two plans (all 2048 under one); over the full 5000 sweeps
+  with a sample every 10, four lattices of each size are followed: L = 256
+  and 512 over all 500 samples and the final state, L = 1024 and 2048 over
+  the first 50 samples (their full oracle run would take minutes); four
+  L = 256 lattices stay equal over 500 sweeps.
 - The L = 32768 single lattice over 20 sweeps on oracle-evolved windows.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -61,7 +67,9 @@ def test_batched_config_sampled_lattices(plan):
     b = ising.Batch(Ls, seeds, hot=True)
     try:
         b.set_plan(**plan)
-        E, M = b.sweep(Ts, 10, every=10, series=True)
+        E1, M1 = b.sweep(Ts, 1, every=1, series=True)
+        E1, M1 = E1.cpu().numpy(), M1.cpu().numpy()
+        E, M = b.sweep(Ts, 9, every=9, series=True)
         E, M = E.cpu().numpy(), M.cpu().numpy()
         rng = np.random.default_rng(4)
         picks = []
@@ -70,9 +78,45 @@ def test_batched_config_sampled_lattices(plan):
             picks += list(rng.choice(idx, 16, replace=False))
         for i in picks:
             s = oracle.init(Ls[i], seeds[i], True)
-            Es, Ms = oracle.sweep(s, seeds[i], 0, 10, Ts[i], every=10)
+            Es, Ms = oracle.sweep(s, seeds[i], 0, 1, Ts[i], every=1)
+            assert E1[i, 0] == Es[0] and M1[i, 0] == Ms[0]
+            Es, Ms = oracle.sweep(s, seeds[i], 1, 9, Ts[i], every=9)
             assert (b.spins(int(i)) == s).all(), (i, Ls[i])
             assert E[i, 0] == Es[0] and M[i, 0] == Ms[0]
+        if plan["resident_max_L"]:  # once: the samples of every lattice
+            t0 = time.time()
+            for i in range(2048):
+                if i % 256 == 0:
+                    print(f"oracle: all 2048 lattices, 10 sweeps: {i} done, {time.time() - t0:.0f} s", flush=True)
+                s = oracle.init(Ls[i], seeds[i], True)
+                Es, Ms = oracle.sweep(s, seeds[i], 0, 1, Ts[i], every=1)
+                assert E1[i, 0] == Es[0] and M1[i, 0] == Ms[0], (i, Ls[i])
+                Es, Ms = oracle.sweep(s, seeds[i], 1, 9, Ts[i], every=9)
+                assert E[i, 0] == Es[0] and M[i, 0] == Ms[0], (i, Ls[i])
+    finally:
+        b.close()
+
+
+def test_batched_config_full_run_sampled_lattices():
+    Ls, Ts, seeds = _batched_config()
+    b = ising.Batch(Ls, seeds, hot=True)
+    try:
+        b.set_plan(resident_max_L=512, resident_block=512, words_per_thread=1, tiled_block=128, sweeps_per_graph=50)
+        E, M = b.sweep(Ts, 5000, every=10, series=True)
+        E, M = E.cpu().numpy(), M.cpu().numpy()
+        rng = np.random.default_rng(5)
+        for size_class in range(4):
+            idx = [i for i in range(2048) if i % 4 == size_class]
+            for i in rng.choice(idx, 4, replace=False):
+                i = int(i)
+                L = Ls[i]
+                n = 5000 if L <= 512 else 500
+                print(f"oracle: lattice {i} L={L} {n} sweeps", flush=True)
+                s = oracle.init(L, seeds[i], True)
+                Es, Ms = oracle.sweep(s, seeds[i], 0, n, Ts[i], every=10)
+                assert (E[i, : n // 10] == Es).all() and (M[i, : n // 10] == Ms).all(), (i, L)
+                if n == 5000:
+                    assert (b.spins(i) == s).all(), (i, L)
     finally:
         b.close()
 
