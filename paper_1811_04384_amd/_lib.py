@@ -109,5 +109,11 @@ def load():
         fn = getattr(lib, name)  # AttributeError here means the library lacks an entry point
         fn.restype = res
         fn.argtypes = args
+    from .build import source_hash
+
+    version = lib.ising_version().decode()
+    if not version.endswith(" src " + source_hash()):
+        raise ImportError(f"{LIB_PATH} ({version}) was built from other sources than the ones beside it; "
+                          "rebuild with `python -m paper_1811_04384_amd.build`")
     _lib = lib
     return lib

@@ -2,6 +2,7 @@
 
     python -m paper_1811_04384_amd.build        # or python paper_1811_04384_amd/build.py
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -24,9 +25,23 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"--offload-arch={ARCH}",
 DEVICE_ONLY = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src, verbose):
+def source_hash() -> str:
+    """Hash of every source the library is built from (csrc/ and the C
+    header); the build embeds it in ising_version() so that a library built
+    from other sources is refused when loaded."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp", ".cpp", ".h")))
+    for f in files + ["../../include/ising.h"]:
+        h.update(f.encode())
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src, verbose, defines):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON + (DEVICE_ONLY if src.endswith(".hip") else []) + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ([HIPCC] + COMMON + defines + (DEVICE_ONLY if src.endswith(".hip") else []) +
+           ["-c", os.path.join(CSRC, src), "-o", obj])
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -41,8 +56,9 @@ def _compile(src, verbose):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    defines = [f'-DISING_SOURCE_HASH="{source_hash()}"']
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, defines), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:

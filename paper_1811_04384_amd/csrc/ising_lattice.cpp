@@ -42,7 +42,10 @@ extern "C" {
 
 const char* ising_last_error(void) { return last_error_ref().c_str(); }
 
-const char* ising_version(void) { return "ising-msc 1.0 (gfx950)"; }
+#ifndef ISING_SOURCE_HASH
+#define ISING_SOURCE_HASH "unknown"
+#endif
+const char* ising_version(void) { return "ising-msc 1.0 (gfx950) src " ISING_SOURCE_HASH; }
 
 int32_t ising_word_rows(int32_t L) { return valid_L(L) ? make_geometry(L).N : 0; }
 

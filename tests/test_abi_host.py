@@ -32,6 +32,14 @@ def test_library_exports_every_declared_symbol():
     assert ising.ising_version().startswith("ising-msc")
 
 
+def test_library_was_built_from_these_sources():
+    # load() refuses a library whose embedded source hash differs; the tests
+    # (and the benchmark) therefore never run a stale build
+    from paper_1811_04384_amd.build import source_hash
+
+    assert ising.ising_version().endswith(" src " + source_hash())
+
+
 def test_geometry_matches_oracle():
     for L in list(range(4, 400, 2)) + [1008, 2016, 4096, 32768, 1 << 18]:
         assert ising.ising_word_rows(L) == oracle.word_rows(L)
