@@ -66,6 +66,13 @@ def _load():
     lib.oracle_random_valid.restype = ctypes.c_int
     lib.oracle_random_iterations.argtypes = [i32, u64, u64, i64, dbl, i32, u8p, i32, i64p, i64p, i32, i32]
     lib.oracle_random_iterations.restype = ctypes.c_int
+    dblp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_replica_uniform.argtypes = [u64, u32, u64, i32, i32, i32, i32]
+    lib.oracle_replica_uniform.restype = u32
+    lib.oracle_replica_init.argtypes = [i32, u64, i32, u8p]
+    lib.oracle_replica_init.restype = ctypes.c_int
+    lib.oracle_replica_sweep.argtypes = [i32, u64, u64, i64, dblp, u8p, i32, i64p, i64p, i32]
+    lib.oracle_replica_sweep.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -262,4 +269,37 @@ def random_iterations(s, seed, t0, n_iter, T, S, every=0, order=0, threads=0):
                                           _i64(Es), _i64(Ms), int(order), int(threads))
     if rc != 0:
         raise ValueError("bad strip-dynamics arguments")
+    return (Es[:k], Ms[:k]) if every > 0 else None
+
+
+REPLICAS = 21
+
+
+def replica_uniform(seed, stream, t, L, k, r, c):
+    """Draw of replica k at site (r, c), sweep t (stream 6 sweeps, 7 hot start)."""
+    return int(_load().oracle_replica_uniform(int(seed), int(stream), int(t), int(L), int(k), int(r), int(c)))
+
+
+def replica_init(L, seed, hot):
+    """21 replicas, uint8 array (21, L, L): 1 = up."""
+    s = np.empty((REPLICAS, L, L), dtype=np.uint8)
+    if _load().oracle_replica_init(int(L), int(seed), int(bool(hot)), _u8(s)) != 0:
+        raise ValueError(f"invalid replica lattice size L={L}")
+    return s
+
+
+def replica_sweep(s, seed, t0, n_sweeps, T, every=0, threads=0):
+    """Advance 21 replicas (array (21, L, L), in place), replica k at T[k].
+    With every > 0 returns (E, M) arrays of shape (n // every, 21)."""
+    assert s.dtype == np.uint8 and s.flags.c_contiguous and s.shape[0] == REPLICAS
+    L = s.shape[1]
+    T = np.ascontiguousarray(np.broadcast_to(np.asarray(T, dtype=np.float64), (REPLICAS,)))
+    n = int(n_sweeps)
+    k = n // every if every > 0 else 0
+    Es = np.zeros((max(k, 1), REPLICAS), dtype=np.int64)
+    Ms = np.zeros((max(k, 1), REPLICAS), dtype=np.int64)
+    rc = _load().oracle_replica_sweep(L, int(seed), int(t0), n, T.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      _u8(s), int(every), _i64(Es), _i64(Ms), int(threads))
+    if rc != 0:
+        raise ValueError("bad replica sweep arguments")
     return (Es[:k], Ms[:k]) if every > 0 else None

@@ -459,3 +459,99 @@ ORACLE_API int oracle_random_iterations(int32_t L, uint64_t seed, uint64_t t0, i
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Replica multi-spin coding: 21 independent L x L lattices (replicas) in    */
+/* one word lattice, the variant of multi-spin coding that packs the same    */
+/* site of different systems into one word (the coding family the paper     */
+/* builds on, Section 3 and its references).  Word (r, c) holds site (r, c) */
+/* of replica k in field 20 - k.  Replicas never interact: each runs the    */
+/* checkerboard Metropolis chain of the sections above at its own           */
+/* temperature T_k, with its own draws.  Here each replica is one byte      */
+/* lattice, s[k L^2 + r L + c].                                              */
+/*                                                                           */
+/* Draw of replica k at site (r, c), sweep t, stream `stream` (6 = sweeps,  */
+/* 7 = hot start at t = 0): Philox key = seed, counter                      */
+/* (t mod 2^32, r L + c', t div 2^32, g + 8 stream) and output q with        */
+/*   k < 20:  g = k div 4, q = k mod 4, c' = c;                             */
+/*   k = 20:  g = 5, q = (c div 2) mod 4, c' = 8 (c div 8) + (c mod 2).      */
+/* r L + c' < 2^32 needs L <= 2^16.                                          */
+/* ------------------------------------------------------------------------ */
+#define REPLICAS 21
+
+static int valid_replica_L(int32_t L) { return L >= 4 && L <= (1 << 16) && (L % 2) == 0; }
+
+ORACLE_API uint32_t oracle_replica_uniform(uint64_t seed, uint32_t stream, uint64_t t, int32_t L, int32_t k,
+                                           int32_t r, int32_t c)
+{
+    uint32_t g, q, col;
+    if (k < 20) {
+        g = (uint32_t)(k >> 2);
+        q = (uint32_t)(k & 3);
+        col = (uint32_t)c;
+    } else {
+        g = 5u;
+        q = (uint32_t)((c >> 1) & 3);
+        col = (uint32_t)((c & ~7) | (c & 1));
+    }
+    uint32_t ctr[4], key[2], out[4];
+    ctr[0] = (uint32_t)t;
+    ctr[1] = (uint32_t)r * (uint32_t)L + col;
+    ctr[2] = (uint32_t)(t >> 32);
+    ctr[3] = g + 8u * stream;
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    oracle_philox4x32_10(ctr, key, out);
+    return out[q];
+}
+
+ORACLE_API int oracle_replica_init(int32_t L, uint64_t seed, int32_t hot, uint8_t* s)
+{
+    if (!valid_replica_L(L)) return -1;
+    const int64_t n = (int64_t)L * L;
+#pragma omp parallel for schedule(static)
+    for (int32_t r = 0; r < L; ++r)
+        for (int32_t k = 0; k < REPLICAS; ++k)
+            for (int32_t c = 0; c < L; ++c)
+                s[k * n + (int64_t)r * L + c] =
+                    hot ? (uint8_t)(oracle_replica_uniform(seed, 7, 0, L, k, r, c) < 0x80000000u) : (uint8_t)1;
+    return 0;
+}
+
+/*
+ * n_sweeps sweeps of every replica, replica k at temperature T[k], starting
+ * at absolute sweep t0; after sweep k (1-based in this call) with
+ * k % every == 0 the 21 replicas' E and M go to E_series[(k/every - 1) 21 +
+ * replica], M_series[...].  Returns 0, or -1 on bad arguments.
+ */
+ORACLE_API int oracle_replica_sweep(int32_t L, uint64_t seed, uint64_t t0, int64_t n_sweeps, const double* T,
+                                    uint8_t* s, int32_t every, int64_t* E_series, int64_t* M_series,
+                                    int32_t nthreads)
+{
+    if (!valid_replica_L(L) || n_sweeps < 0) return -1;
+    for (int32_t k = 0; k < REPLICAS; ++k)
+        if (!(T[k] > 0.0) || isinf(T[k])) return -1;
+    set_threads(nthreads);
+    uint32_t t4[REPLICAS], t8[REPLICAS];
+    for (int32_t k = 0; k < REPLICAS; ++k) oracle_thresholds(T[k], &t4[k], &t8[k]);
+    const int64_t n = (int64_t)L * L;
+    for (int64_t i = 1; i <= n_sweeps; ++i) {
+        uint64_t t = t0 + (uint64_t)(i - 1);
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static)
+            for (int32_t r = 0; r < L; ++r)
+                for (int32_t k = 0; k < REPLICAS; ++k)
+                    for (int32_t c = (r + colour) & 1; c < L; c += 2) {
+                        uint8_t* sk = s + k * n;
+                        int na = count_anti(L, sk, r, c);
+                        uint32_t u = oracle_replica_uniform(seed, 6, t, L, k, r, c);
+                        if (oracle_accept(na, u, t4[k], t8[k])) sk[(int64_t)r * L + c] ^= 1u;
+                    }
+        }
+        if (every > 0 && E_series && M_series && i % every == 0)
+            for (int32_t k = 0; k < REPLICAS; ++k)
+                oracle_observables(L, s + k * n, &E_series[(i / every - 1) * REPLICAS + k],
+                                   &M_series[(i / every - 1) * REPLICAS + k]);
+    }
+    return 0;
+}
