@@ -130,7 +130,7 @@ def kernel_source_hash():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("ising_device.hpp", "ising_kernels.hip", "ising_common.hpp"):
+    for f in ("ising_device.hpp", "ising_kernels.hip", "ising_common.hpp", "ising_moments.hpp"):
         with open(os.path.join(ROOT, "paper_1811_04384_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -108,6 +108,7 @@ int ising_thermodynamics(const ising_moments* m, int32_t L, double T, ising_ther
 typedef struct ising_lattice ising_lattice; /* one lattice (opaque)                 */
 typedef struct ising_batch ising_batch;     /* many lattices, one launch per phase  */
 typedef struct ising_server ising_server;   /* continuous-batching request server   */
+typedef struct ising_replicas ising_replicas; /* 21 replicas sharing one word lattice */
 
 /* ------------------------------------------------------------------ */
 /* Geometry and thresholds (host only, no GPU needed)                   */
@@ -361,6 +362,53 @@ int ising_server_poll(ising_server* s, ising_result* out, int32_t cap, int32_t* 
 int ising_server_stats(ising_server* s, int32_t* queued, int32_t* resident, int32_t* finished, size_t* bytes_in_use);
 
 int ising_server_destroy(ising_server* s);
+
+/* ------------------------------------------------------------------ */
+/* Replica multi-spin coding: 21 independent lattices in one word lattice */
+/* ------------------------------------------------------------------ */
+
+/* The other packing of the multi-spin-coding family the paper builds on
+   (Section 3 and its references): word (r, c), r, c < L, holds site (r, c)
+   of replica k = 0..20 in field 20 - k (bit 3 (20 - k)).  Replicas never
+   interact: replica k runs the checkerboard Metropolis chain of the single
+   lattice (same Table 1 rule, same integer thresholds) at its own
+   temperature T[k], with its own draws: Philox key = seed, counter
+   (t mod 2^32, r L + c', t div 2^32, g + 8 stream), output q, where
+   k < 20: g = k div 4, q = k mod 4, c' = c; k = 20: g = 5,
+   q = (c div 2) mod 4, c' = 8 (c div 8) + (c mod 2); stream 6 for sweeps,
+   7 for the hot start (t = 0; up iff the draw is < 2^31).  The word lattice
+   is uint64 W[L][L], 8 L^2 bytes for 21 L^2 spins.  4 <= L <= 65536, even
+   (r L + c' must fit 32 bits).  E, M arrays hold the 21 replicas in order. */
+int ising_replicas_create(int32_t L, uint64_t seed, int32_t init, void* stream, ising_replicas** out);
+int ising_replicas_destroy(ising_replicas* h);
+
+/* n_sweeps sweeps of every replica, replica k at T[k] (host array of 21). */
+int ising_replicas_sweep(ising_replicas* h, const double* T, int64_t n_sweeps);
+
+/* As ising_replicas_sweep; after the k-th sweep of the call with
+   k % every == 0 the replicas' E and M go to dev_E[(k/every - 1) 21 + i],
+   dev_M[...] (device pointers to (n_sweeps/every) 21 int64 each). */
+int ising_replicas_sweep_measure(ising_replicas* h, const double* T, int64_t n_sweeps, int32_t every, int64_t* dev_E,
+                                 int64_t* dev_M);
+
+/* As ising_replicas_sweep_measure, but the samples are added to the moment
+   sums dev_acc[0..20] (device pointer to 21 ising_moments, zeroed by the
+   caller before the first call). */
+int ising_replicas_sweep_moments(ising_replicas* h, const double* T, int64_t n_sweeps, int32_t every,
+                                 ising_moments* dev_acc);
+
+/* E[21], M[21] of the current state (host arrays).  Synchronises. */
+int ising_replicas_observables(ising_replicas* h, int64_t* E, int64_t* M);
+
+/* Spins of replica k as L*L host bytes (1 = up).  Synchronises. */
+int ising_replicas_get_spins(ising_replicas* h, int32_t k, uint8_t* host_spins);
+
+/* Sweeps done (the absolute index of the next sweep). */
+int ising_replicas_get_sweep_count(ising_replicas* h, uint64_t* t);
+
+/* Words per thread of the half-sweep kernel, 1, 2 or 4 (default 2).
+   Results never depend on it. */
+int ising_replicas_set_plan(ising_replicas* h, int32_t words_per_thread);
 
 #ifdef __cplusplus
 }

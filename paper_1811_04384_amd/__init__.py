@@ -19,7 +19,8 @@ from ._lib import (ISING_COLD, ISING_EAGAIN, ISING_EBUSY, ISING_EHIP, ISING_EINV
                    BatchPlan, Moments, Result, Thermo)
 
 __all__ = [
-    "IsingError", "Lattice", "Batch", "Server", "BatchPlan", "Result", "Moments", "Thermo", "load", "moments_of",
+    "IsingError", "Lattice", "Batch", "Replicas", "Server", "BatchPlan", "Result", "Moments", "Thermo", "load",
+    "moments_of", "REPLICAS",
     "ISING_OK", "ISING_EINVAL", "ISING_ENOMEM", "ISING_EHIP", "ISING_EBUSY", "ISING_EAGAIN", "ISING_COLD", "ISING_HOT",
 ] + sorted(_lib.SIGNATURES)
 
@@ -301,6 +302,62 @@ def ising_batch_autotune(h, T, cache_path=None):
     return p.as_dict()
 
 
+REPLICAS = 21
+
+
+def _temps21(T):
+    return _arr(np.broadcast_to(np.asarray(T, dtype=np.float64), (REPLICAS,)), ctypes.c_double)
+
+
+def ising_replicas_create(L, seed, init, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.load().ising_replicas_create(int(L), int(seed), int(init), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def ising_replicas_destroy(h):
+    _check(_lib.load().ising_replicas_destroy(h))
+
+
+def ising_replicas_sweep(h, T, n_sweeps):
+    T_, pT = _temps21(T)
+    _check(_lib.load().ising_replicas_sweep(h, pT, int(n_sweeps)))
+
+
+def ising_replicas_sweep_measure(h, T, n_sweeps, every, dev_E, dev_M):
+    T_, pT = _temps21(T)
+    _check(_lib.load().ising_replicas_sweep_measure(h, pT, int(n_sweeps), int(every), _ptr(dev_E), _ptr(dev_M)))
+
+
+def ising_replicas_sweep_moments(h, T, n_sweeps, every, dev_acc):
+    T_, pT = _temps21(T)
+    _check(_lib.load().ising_replicas_sweep_moments(h, pT, int(n_sweeps), int(every), _ptr(dev_acc)))
+
+
+def ising_replicas_observables(h):
+    E = np.zeros(REPLICAS, dtype=np.int64)
+    M = np.zeros(REPLICAS, dtype=np.int64)
+    _check(_lib.load().ising_replicas_observables(h, E.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                                  M.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return E, M
+
+
+def ising_replicas_get_spins(h, k, L):
+    out = np.empty((L, L), dtype=np.uint8)
+    _check(_lib.load().ising_replicas_get_spins(h, int(k), _ptr(out)))
+    return out
+
+
+def ising_replicas_get_sweep_count(h):
+    t = ctypes.c_uint64()
+    _check(_lib.load().ising_replicas_get_sweep_count(h, ctypes.byref(t)))
+    return int(t.value)
+
+
+def ising_replicas_set_plan(h, words_per_thread):
+    _check(_lib.load().ising_replicas_set_plan(h, int(words_per_thread)))
+
+
 def ising_server_create(hbm_budget, max_slots, quantum_sweeps, stream=None):
     h = ctypes.c_void_p()
     _check(_lib.load().ising_server_create(int(hbm_budget), int(max_slots), int(quantum_sweeps), _stream(stream),
@@ -508,6 +565,66 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None) is not None:
             ising_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Replicas:
+    """21 independent L x L lattices packed field by field into one word lattice."""
+
+    def __init__(self, L, seed, hot=True, stream=None):
+        self.L = int(L)
+        self.handle = ising_replicas_create(self.L, seed, ISING_HOT if hot else ISING_COLD, stream)
+
+    def sweep(self, T, n):
+        ising_replicas_sweep(self.handle, T, n)
+        return self
+
+    def sweep_measure(self, T, n, every):
+        """Device int64 tensors (E, M) of shape (n // every, 21)."""
+        import torch
+
+        k = int(n) // int(every)
+        E = torch.empty(max(k, 1) * REPLICAS, dtype=torch.int64, device="cuda")
+        M = torch.empty_like(E)
+        ising_replicas_sweep_measure(self.handle, T, n, every, E, M)
+        return E[: k * REPLICAS].view(k, REPLICAS), M[: k * REPLICAS].view(k, REPLICAS)
+
+    def sweep_moments(self, T, n, every, acc=None):
+        """Adds the samples to `acc` (device int64 tensor of 21 x 10, zeroed if None); returns it."""
+        import torch
+
+        if acc is None:
+            acc = torch.zeros(REPLICAS * 10, dtype=torch.int64, device="cuda")
+        ising_replicas_sweep_moments(self.handle, T, n, every, acc)
+        return acc
+
+    def moments(self, acc):
+        raw = acc.detach().cpu().contiguous().numpy().tobytes()
+        size = ctypes.sizeof(Moments)
+        return [Moments.from_buffer_copy(raw[k * size:(k + 1) * size]).as_dict() for k in range(REPLICAS)]
+
+    def observables(self):
+        return ising_replicas_observables(self.handle)
+
+    def spins(self, k):
+        return ising_replicas_get_spins(self.handle, k, self.L)
+
+    @property
+    def t(self):
+        return ising_replicas_get_sweep_count(self.handle)
+
+    def set_plan(self, words_per_thread):
+        ising_replicas_set_plan(self.handle, words_per_thread)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            ising_replicas_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

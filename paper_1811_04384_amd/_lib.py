@@ -85,6 +85,15 @@ SIGNATURES = {
     "ising_batch_set_plan": (c_int, [c_vp, P(BatchPlan)]),
     "ising_batch_get_plan": (c_int, [c_vp, P(BatchPlan)]),
     "ising_batch_autotune": (c_int, [c_vp, P(c_dbl), c_char_p, P(BatchPlan)]),
+    "ising_replicas_create": (c_int, [c_i32, c_u64, c_i32, c_vp, P(c_vp)]),
+    "ising_replicas_destroy": (c_int, [c_vp]),
+    "ising_replicas_sweep": (c_int, [c_vp, P(c_dbl), c_i64]),
+    "ising_replicas_sweep_measure": (c_int, [c_vp, P(c_dbl), c_i64, c_i32, c_vp, c_vp]),
+    "ising_replicas_sweep_moments": (c_int, [c_vp, P(c_dbl), c_i64, c_i32, c_vp]),
+    "ising_replicas_observables": (c_int, [c_vp, P(c_i64), P(c_i64)]),
+    "ising_replicas_get_spins": (c_int, [c_vp, c_i32, c_vp]),
+    "ising_replicas_get_sweep_count": (c_int, [c_vp, P(c_u64)]),
+    "ising_replicas_set_plan": (c_int, [c_vp, c_i32]),
     "ising_server_create": (c_int, [c_sz, c_i32, c_i32, c_vp, P(c_vp)]),
     "ising_server_submit": (c_int, [c_vp, c_u64, c_i32, c_dbl, c_i64, c_u64, c_i32]),
     "ising_server_step": (c_int, [c_vp, P(c_i32)]),

@@ -14,7 +14,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libising.so")
 ARCH = "gfx950"
 
-SOURCES = [s for s in ["ising_kernels.hip", "ising_strips.hip", "ising_lattice.cpp", "ising_batch.cpp", "ising_server.cpp"]
+SOURCES = [s for s in ["ising_kernels.hip", "ising_strips.hip", "ising_replicas.hip", "ising_lattice.cpp",
+                       "ising_batch.cpp", "ising_server.cpp", "ising_replicas.cpp"]
            if os.path.exists(os.path.join(CSRC, s))]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -39,7 +40,7 @@ def source_hash() -> str:
 
 
 def _compile(src, verbose, defines):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, src.replace(".", "_") + ".o")  # x.hip and x.cpp get distinct objects
     cmd = ([HIPCC] + COMMON + defines + (DEVICE_ONLY if src.endswith(".hip") else []) +
            ["-c", os.path.join(CSRC, src), "-o", obj])
     if verbose:
