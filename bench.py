@@ -16,7 +16,8 @@ L = 4096 run, the batched mixed-L run, the L = 64 temperature scan, heating
 scans of L = 1008 replicas with the lattice carried over (energy and specific
 heat per temperature), the paper's own 101-temperature scan of its L = 84
 lattice, the paper's three Table 2 cases run with its own random-pick strip
-dynamics, and a served request stream with p50/p99 latency.
+dynamics, 21 replicas of L = 8192 packed field by field into one word
+lattice, and a served request stream with p50/p99 latency.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -383,6 +384,35 @@ def run_paper_cases(ising, strip_cols=2, T=2.269):
             **out}
 
 
+def run_replicas(ising, L=8192, sweeps=200, seed=21):
+    """Replica multi-spin coding: 21 independent L = 8192 lattices (1.41e9
+    spins) packed field by field into one 537 MB word lattice, replica k at
+    T = 1.5 + 0.1 k, hot start; 200 sweeps, then the 21 replicas' E and M.
+    Every words-per-thread plan is timed; the best is reported."""
+    import torch
+
+    Ts = [round(1.5 + 0.1 * k, 10) for k in range(21)]
+    rep = ising.Replicas(L, seed, hot=True)
+    rates = {}
+    for wpt in (1, 2, 4):
+        rep.set_plan(wpt)
+        rep.sweep(Ts, 5)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        rep.sweep(Ts, sweeps)
+        e1.record()
+        torch.cuda.synchronize()
+        rates[wpt] = 21 * L * L * sweeps / (e0.elapsed_time(e1) * 1e6)
+    E, M = rep.observables()
+    rep.close()
+    best = max(rates, key=rates.get)
+    return {"workload": f"21 replicas of L={L} in one word lattice, T=1.5..3.5 step 0.1, hot start, {sweeps} sweeps",
+            "value": round(rates[best], 2), "unit": UNIT, "words_per_thread": best,
+            "by_words_per_thread": {str(k): round(v, 2) for k, v in rates.items()},
+            "e_per_spin": [round(int(e) / L ** 2, 4) for e in E]}
+
+
 def run_serving(ising, rate=25.0, duration=10.0, quantum=100, seed=2026):
     """Poisson request stream: L = 2^U{7..12}, T ~ U[1.5, 3.5], sweeps ~
     U{1000..20000}, hot start with seed = request id; continuous batching."""
@@ -442,7 +472,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=SWEEPS_MAIN, help="sweeps per temperature (headline: 2000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--secondary",
-                    default="plain4096,graph4096,batched,scan64,heating_scan,paper_scan,paper_cases,serving",
+                    default="plain4096,graph4096,batched,scan64,heating_scan,paper_scan,paper_cases,replicas,serving",
                     help="comma list of secondary workloads, or 'none'")
     ap.add_argument("--serving-rate", type=float, default=25.0)
     ap.add_argument("--serving-duration", type=float, default=10.0)
@@ -507,6 +537,8 @@ def main():
             secondary[name] = run_paper_scan(ising)
         elif name == "paper_cases":
             secondary[name] = run_paper_cases(ising)
+        elif name == "replicas":
+            secondary[name] = run_replicas(ising)
         elif name == "serving":
             secondary[name] = run_serving(ising, args.serving_rate, args.serving_duration, args.serving_quantum)
         log(f"  {secondary.get(name)}")
