@@ -144,19 +144,42 @@ __device__ __forceinline__ void append_draw(Codes& c, int p, uint32_t u, uint32_
     else c.lo = append_accept(c.lo, u, t4, t8);
 }
 
-// Flip mask of a word.  a..d = w XOR neighbour (only bit 3k meaningful);
-// n = number of set inputs per field.  A spin flips iff n >= 2 (dE <= 0), or
-// n = 1 and code >= 1 (dE = +4), or n = 0 and code = 2 (dE = +8) (Table 1
-// and the Metropolis rule of Section 2).  With code bits c0 = [code = 1] and
-// c1 = [code = 2]: flip = c1 | ((c0 | c1) & n>=1) | n>=2.
+// Three-input bitwise operation with truth table TT (operand bits x, y, z
+// index bit 4x + 2y + z of TT).
+template <int TT>
+__device__ __forceinline__ uint32_t lop3(uint32_t x, uint32_t y, uint32_t z) {
+    return __builtin_amdgcn_bitop3_b32(x, y, z, TT);
+}
+
+// One 32-bit half of the flip mask.  A spin flips iff n >= 2 antiparallel
+// neighbours (dE <= 0), or n = 1 and code >= 1 (dE = +4), or n = 0 and
+// code = 2 (dE = +8) (Table 1 and the Metropolis rule of Section 2).  With
+// t = [differs from up or down], p = [differs from both] and t', p' the
+// same for left and right: n >= 1 is t | t', n >= 2 is p | p' | (t & t').
+// With code bits c0 = [code = 1], c1 = [code = 2]:
+// flip = c1 | ((c0 | c1) & n>=1) | n>=2.
+__device__ __forceinline__ uint32_t flip_half(uint32_t w, uint32_t up, uint32_t dn, uint32_t lf, uint32_t rt,
+                                              uint32_t c0, uint32_t c1, uint32_t live) {
+    const uint32_t t1 = lop3<0x7E>(w, up, dn);  // (w ^ up) | (w ^ dn)
+    const uint32_t p1 = lop3<0x18>(w, up, dn);  // (w ^ up) & (w ^ dn)
+    const uint32_t t2 = lop3<0x7E>(w, lf, rt);
+    const uint32_t p2 = lop3<0x18>(w, lf, rt);
+    const uint32_t ge1 = t1 | t2;
+    const uint32_t ge2 = lop3<0xFE>(p1, p2, t1 & t2);  // or of the three
+    const uint32_t x = lop3<0xA8>(c0, c1, ge1);         // (c0 | c1) & ge1
+    return lop3<0xFE>(c1, x, ge2) & live;
+}
+
+// Flip mask of a word (only bit 3k of each field is meaningful).
 __device__ __forceinline__ uint64_t flip_mask(uint64_t w, uint64_t up, uint64_t dn, uint64_t lf, uint64_t rt,
                                               uint64_t codes, uint64_t live) {
-    const uint64_t a = w ^ up, b = w ^ dn, c = w ^ lf, d = w ^ rt;
-    const uint64_t ab_or = a | b, cd_or = c | d;
-    const uint64_t ge1 = ab_or | cd_or;
-    const uint64_t ge2 = (a & b) | (c & d) | (ab_or & cd_or);
     const uint64_t c1 = codes >> 1;
-    return (c1 | ((codes | c1) & ge1) | ge2) & live;
+    const uint32_t lo = flip_half((uint32_t)w, (uint32_t)up, (uint32_t)dn, (uint32_t)lf, (uint32_t)rt, (uint32_t)codes,
+                                  (uint32_t)c1, (uint32_t)live);
+    const uint32_t hi = flip_half((uint32_t)(w >> 32), (uint32_t)(up >> 32), (uint32_t)(dn >> 32), (uint32_t)(lf >> 32),
+                                  (uint32_t)(rt >> 32), (uint32_t)(codes >> 32), (uint32_t)(c1 >> 32),
+                                  (uint32_t)(live >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint64_t assemble_codes(const Codes& c) {
