@@ -237,8 +237,8 @@ int ising_words(ising_lattice* h, void** dev_words, size_t* bytes);
 
 /* Kernel variant used by ising_sweep*: words_per_thread in {1, 2, 4} (same-
    colour words of one row handled by one thread; 4 lets one Philox call serve
-   position 20 of four words) and block in {64, 128, 256, 512, 1024}.  Results
-   never depend on the choice. */
+   position 20 of four words) and block a multiple of 64 in [64, 256].
+   Results never depend on the choice. */
 int ising_set_plan(ising_lattice* h, int32_t words_per_thread, int32_t block);
 int ising_get_plan(ising_lattice* h, int32_t* words_per_thread, int32_t* block);
 

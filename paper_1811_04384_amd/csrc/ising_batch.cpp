@@ -179,7 +179,9 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
         b->units[i] = u;
         b->off32 = b->off32 && fits_off32(g);
         b->part_begin[i] = (int32_t)waves.size();
-        for (int64_t u0 = 0; u0 < u; u0 += 64) waves.push_back({i, (int32_t)u0});
+        const int32_t segs = segments_per_row(g.L, p.words_per_thread);
+        for (int32_t I = 0; I < g.N; ++I)
+            for (int32_t s0 = 0; s0 < segs; s0 += 64) waves.push_back({i, I, s0});
         b->part_count[i] = (int32_t)waves.size() - b->part_begin[i];
     }
     b->n_waves = (int64_t)waves.size();

@@ -87,11 +87,13 @@ struct LatticeState {
     int64_t last_E, last_M;   // most recent sample or observation
 };
 
-// One wavefront of a tiled half-sweep launch: 64 consecutive work units of
-// one lattice.
+// One wavefront of a tiled half-sweep launch: 64 consecutive row segments
+// of one word row of one lattice (segments beyond the row's `segs` idle), so
+// the lattice and the row are wave-uniform.
 struct WaveItem {
     int32_t lattice;
-    int32_t unit0;  // first unit handled by lane 0 (units beyond `units` idle)
+    int32_t row;   // word row I
+    int32_t seg0;  // segment handled by lane 0
 };
 
 // Partial sums of one wavefront: antiparallel bonds and up spins.

@@ -78,13 +78,14 @@ struct WordPtr {
 
 template <int WPT, bool MEASURE, bool OFF32>
 __global__ void __launch_bounds__(kTiledMaxBlock)
-    k_halfsweep_single(uint64_t* __restrict__ W, SweepArgs a, int32_t segs, uint32_t units, int colour,
+    k_halfsweep_single(uint64_t* __restrict__ W, SweepArgs a, int32_t segs, int colour,
                        Partial* __restrict__ partials) {
-    const uint32_t unit = blockIdx.x * blockDim.x + threadIdx.x;
+    // word row = blockIdx.y: the row, its wrap cases, live slots and
+    // counter base are wave-uniform (scalar unit); segment along x
+    const int I = (int)blockIdx.y;
+    const int seg = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     uint32_t anti = 0, ups = 0;
-    if (unit < units) {
-        const int I = (int)(unit / (uint32_t)segs);
-        const int seg = (int)(unit - (uint32_t)I * (uint32_t)segs);
+    if (seg < segs) {
         const int J0 = seg * 2 * WPT + ((I + colour) & 1);
         const WordPtr<OFF32> p{W, (uint32_t)a.L};
         auto ld = [&](int i, int j) { return *p.at(i, j); };
@@ -94,7 +95,8 @@ __global__ void __launch_bounds__(kTiledMaxBlock)
     if (MEASURE) {
         anti = wave_sum_u32(anti);
         ups = wave_sum_u32(ups);
-        if (lane_id() == 0) partials[unit >> 6] = {anti, ups};
+        const uint32_t wave = ((blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+        if (lane_id() == 0) partials[wave] = {anti, ups};
     }
 }
 
@@ -118,12 +120,10 @@ __global__ void __launch_bounds__(kTiledMaxBlock)
     }
     const uint64_t t = states[item.lattice].t + sweep_off;
     const SweepArgs a = {d.L, d.N, d.istar, d.sh_star, (uint32_t)t, (uint32_t)(t >> 32), d.k0, d.k1, d.t4, d.t8};
-    const uint32_t unit = (uint32_t)item.unit0 + (uint32_t)lane_id();
+    const int I = item.row;
+    const int seg = item.seg0 + (int)lane_id();
     uint32_t anti = 0, ups = 0;
-    if (unit < (uint32_t)d.units) {
-        const int segs = d.segs;
-        const int I = (int)(unit / (uint32_t)segs);
-        const int seg = (int)(unit - (uint32_t)I * (uint32_t)segs);
+    if (seg < d.segs) {
         const int J0 = seg * 2 * WPT + ((I + colour) & 1);
         const WordPtr<OFF32> p{d.W, (uint32_t)a.L};
         auto ld = [&](int i, int j) { return *p.at(i, j); };
@@ -438,23 +438,20 @@ hipError_t launch_init(uint64_t* W, const Geometry& g, uint64_t seed, int hot, h
 }
 
 int64_t halfsweep_single_waves(const Geometry& g, int wpt, int block) {
-    return (int64_t)grid_for((uint64_t)units_per_colour(g, wpt), block) * block / 64;
+    return (int64_t)grid_for((uint64_t)segments_per_row(g.L, wpt), block) * g.N * (block / 64);
 }
 
 hipError_t launch_halfsweep_single(int wpt, int block, uint64_t* W, const SweepArgs& a, int colour,
                                    Partial* partials, int64_t* n_waves, hipStream_t s) {
     const Geometry g = {a.L, a.N, a.istar, a.sh_star};
     const int32_t segs = segments_per_row(a.L, wpt);
-    const uint32_t units = (uint32_t)units_per_colour(g, wpt);
-    const dim3 grid(grid_for(units, block)), blk(block);
-    if (n_waves) *n_waves = (int64_t)grid.x * block / 64;
+    const dim3 grid(grid_for((uint64_t)segs, block), (unsigned)a.N), blk(block);
+    if (n_waves) *n_waves = halfsweep_single_waves(g, wpt, block);
     const bool m = partials != nullptr;
     const bool off32 = (uint64_t)g.N * (uint64_t)g.L * 8u < (1ull << 32);
 #define ISING_LAUNCH_HS2(WPT_, O_)                                                                                \
-    if (m) hipLaunchKernelGGL((k_halfsweep_single<WPT_, true, O_>), grid, blk, 0, s, W, a, segs, units, colour,   \
-                              partials);                                                                          \
-    else hipLaunchKernelGGL((k_halfsweep_single<WPT_, false, O_>), grid, blk, 0, s, W, a, segs, units, colour,    \
-                            partials);
+    if (m) hipLaunchKernelGGL((k_halfsweep_single<WPT_, true, O_>), grid, blk, 0, s, W, a, segs, colour, partials); \
+    else hipLaunchKernelGGL((k_halfsweep_single<WPT_, false, O_>), grid, blk, 0, s, W, a, segs, colour, partials);
 #define ISING_LAUNCH_HS(WPT_)            \
     if (off32) {                         \
         ISING_LAUNCH_HS2(WPT_, true)     \

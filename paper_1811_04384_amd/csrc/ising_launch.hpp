@@ -14,6 +14,11 @@ inline int32_t segments_per_row(int32_t L, int32_t wpt) { return (L + 2 * wpt - 
 inline int64_t units_per_colour(const Geometry& g, int32_t wpt) {
     return (int64_t)g.N * segments_per_row(g.L, wpt);
 }
+// Wavefronts of a tiled half-sweep of one lattice: every word row starts a
+// new wavefront.
+inline int64_t waves_per_colour(const Geometry& g, int32_t wpt) {
+    return (int64_t)g.N * ((segments_per_row(g.L, wpt) + 63) / 64);
+}
 
 // Spins of a fresh lattice: cold (all up) or hot (Philox stream 0 draw < 2^31).
 hipError_t launch_init(uint64_t* W, const Geometry& g, uint64_t seed, int hot, hipStream_t s);

@@ -200,7 +200,7 @@ int enqueue_quantum(ising_server* s) {
         const Slot& sl = sc.slots()[i];
         if (!sl.active || sl.planned <= 0) continue;
         const Geometry g = make_geometry(sl.req.L);
-        if (!is_resident(s, g)) n_waves += (units_per_colour(g, kServerWpt) + 63) / 64;
+        if (!is_resident(s, g)) n_waves += waves_per_colour(g, kServerWpt);
     }
     int rc = grow_waves(s, st, std::max<int64_t>(n_waves, 1));
     if (rc != ISING_OK) return rc;
@@ -234,7 +234,8 @@ int enqueue_quantum(ising_server* s) {
             d.units = units_per_colour(g, kServerWpt);
             off32 = off32 && fits_off32(g);
             d.part_begin = (int32_t)n_waves;
-            for (int64_t u0 = 0; u0 < d.units; u0 += 64) st.waves[n_waves++] = {i, (int32_t)u0};
+            for (int32_t I = 0; I < g.N; ++I)
+                for (int32_t s0 = 0; s0 < d.segs; s0 += 64) st.waves[n_waves++] = {i, I, s0};
             d.part_count = (int32_t)(n_waves - d.part_begin);
         }
     }
