@@ -50,6 +50,9 @@ __device__ __forceinline__ U4 philox_lane_c1(uint32_t c0, uint32_t c1, uint32_t 
         if (r < 3) {
             n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
             n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        } else if (r == 3) {  // word 3 is still wave-uniform: c3 ^ k1 on the scalar unit
+            n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+            n2 = (uint32_t)(pa >> 32) ^ (c3 ^ k1);
         } else {
             n0 = xor3((uint32_t)(pb >> 32), c1, k0);
             n2 = xor3((uint32_t)(pa >> 32), c3, k1);
@@ -138,9 +141,26 @@ __device__ __forceinline__ uint32_t append_accept(uint32_t acc, uint32_t u, uint
     return acc;
 }
 
+// accept_code(u) as four VALU instructions (the first code of an
+// accumulator needs no shift-or).
+__device__ __forceinline__ uint32_t first_accept(uint32_t u, uint32_t t4, uint32_t t8) {
+    uint32_t x;
+    uint64_t m4, m8;
+    asm("v_cmp_gt_u32_e64 %[m4], %[t4], %[u]\n\t"
+        "v_cmp_gt_u32_e64 %[m8], %[t8], %[u]\n\t"
+        "s_nop 1\n\t"
+        "v_cndmask_b32_e64 %[x], 0, 1, %[m4]\n\t"
+        "v_cndmask_b32_e64 %[x], %[x], 2, %[m8]"
+        : [x] "=&v"(x), [m4] "=&s"(m4), [m8] "=&s"(m8)
+        : [u] "v"(u), [t4] "s"(t4), [t8] "s"(t8));
+    return x;
+}
+
 __device__ __forceinline__ void append_draw(Codes& c, int p, uint32_t u, uint32_t t4, uint32_t t8) {
-    if (p < 10) c.hi = append_accept(c.hi, u, t4, t8);
-    else if (p == 10) c.mid = accept_code(u, t4, t8);
+    if (p == 0) c.hi = first_accept(u, t4, t8);
+    else if (p < 10) c.hi = append_accept(c.hi, u, t4, t8);
+    else if (p == 10) c.mid = first_accept(u, t4, t8);
+    else if (p == 11) c.lo = first_accept(u, t4, t8);
     else c.lo = append_accept(c.lo, u, t4, t8);
 }
 
