@@ -358,8 +358,8 @@ int create_impl(int32_t n, const int32_t* L, const uint64_t* seed, const int32_t
         for (int32_t i = 0; i < n; ++i)
             if (lattice_bytes(b->geo[i]) <= lim && b->geo[i].L <= 256) p.resident_max_L = std::max(p.resident_max_L, b->geo[i].L);
         p.resident_block = 256;
-        p.words_per_thread = 4;
-        p.tiled_block = 256;
+        p.words_per_thread = 1;
+        p.tiled_block = 128;
         p.sweeps_per_graph = 50;
     }
     int rc = apply_plan(b, p);
