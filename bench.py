@@ -413,7 +413,7 @@ def run_replicas(ising, L=8192, sweeps=200, seed=21):
             "e_per_spin": [round(int(e) / L ** 2, 4) for e in E]}
 
 
-def run_serving(ising, rate=25.0, duration=10.0, quantum=100, seed=2026):
+def run_serving(ising, rate=25.0, duration=10.0, quantum=100, seed=2026, slots=128):
     """Poisson request stream: L = 2^U{7..12}, T ~ U[1.5, 3.5], sweeps ~
     U{1000..20000}, hot start with seed = request id; continuous batching."""
     import numpy as np
@@ -429,7 +429,7 @@ def run_serving(ising, rate=25.0, duration=10.0, quantum=100, seed=2026):
         arrivals.append((t, rid, int(2 ** rng.integers(7, 13)), float(rng.uniform(1.5, 3.5)),
                          int(rng.integers(1000, 20001))))
         rid += 1
-    srv = ising.Server(hbm_budget=16 << 30, max_slots=8192, quantum_sweeps=quantum)
+    srv = ising.Server(hbm_budget=16 << 30, max_slots=slots, quantum_sweeps=quantum)
     lat_s = []
     attempts = 0
     i = 0
@@ -480,6 +480,8 @@ def main():
                     help="only run the served stream at each comma-separated rate (req/s) for --serving-duration "
                          "seconds and print one JSON line per rate")
     ap.add_argument("--serving-quantum", type=int, default=100)
+    ap.add_argument("--serving-slots", type=int, default=128,
+                    help="requests resident at once (the rest wait in FIFO order)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run 10 device-to-device copies of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -502,8 +504,9 @@ def main():
     if args.serving_sweep:
         for rate in [float(x) for x in args.serving_sweep.split(",")]:
             log(f"serving at {rate:g} req/s for {args.serving_duration:g} s")
-            print(json.dumps({"rate_req_s": rate, "quantum": args.serving_quantum,
-                              **run_serving(ising, rate, args.serving_duration, args.serving_quantum)}), flush=True)
+            print(json.dumps({"rate_req_s": rate, "quantum": args.serving_quantum, "slots": args.serving_slots,
+                              **run_serving(ising, rate, args.serving_duration, args.serving_quantum,
+                                            slots=args.serving_slots)}), flush=True)
         return
     if args.copy_probe:
         src = torch.empty(args.copy_probe // 4, dtype=torch.int32, device="cuda").fill_(1)
@@ -540,7 +543,8 @@ def main():
         elif name == "replicas":
             secondary[name] = run_replicas(ising)
         elif name == "serving":
-            secondary[name] = run_serving(ising, args.serving_rate, args.serving_duration, args.serving_quantum)
+            secondary[name] = run_serving(ising, args.serving_rate, args.serving_duration, args.serving_quantum,
+                                          slots=args.serving_slots)
         log(f"  {secondary.get(name)}")
 
     cpu = None
