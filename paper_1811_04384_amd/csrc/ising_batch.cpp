@@ -222,21 +222,27 @@ int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipS
     if (b->n_glb)
         ISING_HIP(launch_resident(p.words_per_thread, p.resident_block, b->d_desc, b->d_state, b->d_ids_glb, b->n_glb,
                                   k, every, 0, rs));
+    // A measured sweep s is finalized by the next launch on s0: the colour-0
+    // half-sweep of sweep s + 1, or the chunk's end.
+    auto measured = [&](int32_t s) { return every > 0 && s >= 0 && (s + 1) % every == 0; };
     if (b->n_tiled) {
         for (int32_t s = 0; s < k; ++s) {
-            const bool meas = every > 0 && (s + 1) % every == 0;
             ISING_HIP(launch_halfsweep_multi(p.words_per_thread, p.tiled_block, b->d_desc, b->d_state, b->d_waves,
-                                             b->n_waves, 0, (uint32_t)s, nullptr, b->off32, s0));
+                                             b->n_waves, 0, (uint32_t)s, nullptr,
+                                             measured(s - 1) ? b->d_partials : nullptr, (uint32_t)(s - 1), b->off32,
+                                             s0));
             ISING_HIP(launch_halfsweep_multi(p.words_per_thread, p.tiled_block, b->d_desc, b->d_state, b->d_waves,
-                                             b->n_waves, 1, (uint32_t)s, meas ? b->d_partials : nullptr, b->off32, s0));
-            if (meas) ISING_HIP(launch_finalize_multi(b->d_desc, b->d_state, b->n, b->d_partials, (uint32_t)s, s0));
+                                             b->n_waves, 1, (uint32_t)s, measured(s) ? b->d_partials : nullptr,
+                                             nullptr, 0, b->off32, s0));
         }
     }
     if (fork) {
         ISING_HIP(hipEventRecord(b->join_ev, s1));
         ISING_HIP(hipStreamWaitEvent(s0, b->join_ev, 0));
     }
-    ISING_HIP(launch_advance(b->d_desc, b->d_state, b->n, (uint32_t)k, s0));
+    const bool fin_last = b->n_tiled > 0 && measured(k - 1);
+    ISING_HIP(launch_chunk_end(b->d_desc, b->d_state, b->n, fin_last ? b->d_partials : nullptr, (uint32_t)(k - 1),
+                               (uint32_t)k, s0));
     return ISING_OK;
 }
 

@@ -100,25 +100,61 @@ __global__ void __launch_bounds__(kTiledMaxBlock)
     }
 }
 
+// E = 2 A - 2 L^2 (A antiparallel bonds out of 2 L^2), M = 2 U - L^2.
+__device__ __forceinline__ void energy_magnetisation(uint64_t anti, uint64_t ups, int32_t L, int64_t& E, int64_t& M) {
+    const int64_t n = (int64_t)L * (int64_t)L;
+    E = 2 * (int64_t)anti - 2 * n;
+    M = 2 * (int64_t)ups - n;
+}
+
+// One wavefront turns a tiled lattice's wavefront partials of a measured
+// sweep into its sample: series entry, moment sums, last E and M.
+__device__ __forceinline__ void finalize_lattice(const LatticeDesc& d, LatticeState& st,
+                                                 const Partial* __restrict__ partials) {
+    unsigned long long anti = 0, ups = 0;
+    for (int i = (int)lane_id(); i < d.part_count; i += 64) {
+        anti += partials[d.part_begin + i].anti;
+        ups += partials[d.part_begin + i].ups;
+    }
+    anti = wave_sum_u64(anti);
+    ups = wave_sum_u64(ups);
+    if (lane_id() == 0) {
+        int64_t E, M;
+        energy_magnetisation(anti, ups, d.L, E, M);
+        const int64_t idx = st.series_idx;
+        st.last_E = E;
+        st.last_M = M;
+        add_sample(st.mom, E, M);
+        if (d.series_E) d.series_E[idx] = E;
+        if (d.series_M) d.series_M[idx] = M;
+        st.series_idx = idx + 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Half-sweep over a table of wavefronts covering many lattices.  Every
 // wavefront belongs to one lattice, so the lattice's parameters (key, sweep
-// index, thresholds) are wave-uniform and live in scalar registers.
+// index, thresholds) are wave-uniform and live in scalar registers.  With
+// fin_partials set, the first wavefront of every lattice first finalizes the
+// lattice's measured sweep fin_off from the partials that an earlier launch
+// left (the launch boundary orders them), which saves a launch per sample.
 // ---------------------------------------------------------------------------
 template <int WPT, bool MEASURE, bool OFF32>
 __global__ void __launch_bounds__(kTiledMaxBlock)
-    k_halfsweep_multi(const LatticeDesc* __restrict__ descs, const LatticeState* __restrict__ states,
+    k_halfsweep_multi(const LatticeDesc* __restrict__ descs, LatticeState* __restrict__ states,
                       const WaveItem* __restrict__ waves, uint32_t n_waves, int colour, uint32_t sweep_off,
-                      Partial* __restrict__ partials) {
+                      Partial* __restrict__ partials, const Partial* __restrict__ fin_partials, uint32_t fin_off) {
     const uint32_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (wave >= n_waves) return;
     const WaveItem item = waves[wave];
     const LatticeDesc& d = descs[item.lattice];
+    const uint64_t t = states[item.lattice].t + sweep_off;  // read before the finalize's stores: a scalar load
+    if (fin_partials && wave == (uint32_t)d.part_begin && fin_off < (uint32_t)d.sweep_limit)
+        finalize_lattice(d, states[item.lattice], fin_partials);
     if (sweep_off >= (uint32_t)d.sweep_limit) {  // this lattice has finished its sweeps of the chunk
         if (MEASURE && lane_id() == 0) partials[wave] = {0u, 0u};
         return;
     }
-    const uint64_t t = states[item.lattice].t + sweep_off;
     const SweepArgs a = {d.L, d.N, d.istar, d.sh_star, (uint32_t)t, (uint32_t)(t >> 32), d.k0, d.k1, d.t4, d.t8};
     const int I = item.row;
     const int seg = item.seg0 + (int)lane_id();
@@ -157,13 +193,6 @@ __device__ __forceinline__ void block_sum2(uint64_t& x, uint64_t& y, uint64_t* r
         y = sy;
     }
     __syncthreads();
-}
-
-// E = 2 A - 2 L^2 (A antiparallel bonds out of 2 L^2), M = 2 U - L^2.
-__device__ __forceinline__ void energy_magnetisation(uint64_t anti, uint64_t ups, int32_t L, int64_t& E, int64_t& M) {
-    const int64_t n = (int64_t)L * (int64_t)L;
-    E = 2 * (int64_t)anti - 2 * n;
-    M = 2 * (int64_t)ups - n;
 }
 
 // Grid reduction of one lattice's wavefront partials: every workgroup sums a
@@ -216,36 +245,17 @@ __global__ void __launch_bounds__(256) k_finalize_single(const Partial* __restri
     }
 }
 
-__global__ void __launch_bounds__(256) k_finalize_multi(const LatticeDesc* __restrict__ descs,
-                                                        LatticeState* __restrict__ states,
-                                                        const Partial* __restrict__ partials, uint32_t sweep_off) {
-    __shared__ uint64_t red[32];
+// End of a chunk of sweeps, one wavefront per lattice: finalize the tiled
+// lattices' measured sweep fin_off (with fin_partials set) and advance every
+// lattice's sweep counter by the sweeps it ran.
+__global__ void __launch_bounds__(64) k_chunk_end(const LatticeDesc* __restrict__ descs,
+                                                  LatticeState* __restrict__ states,
+                                                  const Partial* __restrict__ fin_partials, uint32_t fin_off,
+                                                  uint32_t k) {
     const LatticeDesc& d = descs[blockIdx.x];
-    if (d.resident || sweep_off >= (uint32_t)d.sweep_limit) return;
-    uint64_t anti = 0, ups = 0;
-    for (int i = threadIdx.x; i < d.part_count; i += blockDim.x) {
-        anti += partials[d.part_begin + i].anti;
-        ups += partials[d.part_begin + i].ups;
-    }
-    block_sum2(anti, ups, red);
-    if (threadIdx.x == 0) {
-        LatticeState& st = states[blockIdx.x];
-        int64_t E, M;
-        energy_magnetisation(anti, ups, d.L, E, M);
-        const int64_t idx = st.series_idx;
-        st.last_E = E;
-        st.last_M = M;
-        add_sample(st.mom, E, M);
-        if (d.series_E) d.series_E[idx] = E;
-        if (d.series_M) d.series_M[idx] = M;
-        st.series_idx = idx + 1;
-    }
-}
-
-__global__ void k_advance(const LatticeDesc* __restrict__ descs, LatticeState* __restrict__ states, int32_t n,
-                          uint32_t k) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) states[i].t += min(k, (uint32_t)descs[i].sweep_limit);
+    LatticeState& st = states[blockIdx.x];
+    if (fin_partials && !d.resident && fin_off < (uint32_t)d.sweep_limit) finalize_lattice(d, st, fin_partials);
+    if (threadIdx.x == 0) st.t += min(k, (uint32_t)d.sweep_limit);
 }
 
 __global__ void k_reset_sums(LatticeState* __restrict__ states, int32_t n) {
@@ -506,18 +516,19 @@ hipError_t launch_pack(const uint8_t* in, const Geometry& g, uint64_t* W, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, const LatticeState* states,
+hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, LatticeState* states,
                                   const WaveItem* waves, int64_t n_waves, int colour, uint32_t sweep_off,
-                                  Partial* partials, bool off32, hipStream_t s) {
+                                  Partial* partials, const Partial* fin_partials, uint32_t fin_off, bool off32,
+                                  hipStream_t s) {
     if (n_waves <= 0) return hipSuccess;
     const dim3 grid(grid_for((uint64_t)n_waves * 64, block)), blk(block);
     const bool m = partials != nullptr;
     const uint32_t nw = (uint32_t)n_waves;
 #define ISING_LAUNCH_HM2(WPT_, O_)                                                                                  \
     if (m) hipLaunchKernelGGL((k_halfsweep_multi<WPT_, true, O_>), grid, blk, 0, s, descs, states, waves, nw,       \
-                              colour, sweep_off, partials);                                                         \
+                              colour, sweep_off, partials, fin_partials, fin_off);                                  \
     else hipLaunchKernelGGL((k_halfsweep_multi<WPT_, false, O_>), grid, blk, 0, s, descs, states, waves, nw,        \
-                            colour, sweep_off, partials);
+                            colour, sweep_off, partials, fin_partials, fin_off);
 #define ISING_LAUNCH_HM(WPT_)           \
     if (off32) {                        \
         ISING_LAUNCH_HM2(WPT_, true)    \
@@ -535,16 +546,10 @@ hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, 
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_multi(const LatticeDesc* descs, LatticeState* states, int32_t n_lat,
-                                 const Partial* partials, uint32_t sweep_off, hipStream_t s) {
+hipError_t launch_chunk_end(const LatticeDesc* descs, LatticeState* states, int32_t n_lat,
+                            const Partial* fin_partials, uint32_t fin_off, uint32_t k, hipStream_t s) {
     if (n_lat <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize_multi, dim3(n_lat), dim3(256), 0, s, descs, states, partials, sweep_off);
-    return hipGetLastError();
-}
-
-hipError_t launch_advance(const LatticeDesc* descs, LatticeState* states, int32_t n_lat, uint32_t k, hipStream_t s) {
-    if (n_lat <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_advance, dim3(grid_for(n_lat, 256)), dim3(256), 0, s, descs, states, n_lat, k);
+    hipLaunchKernelGGL(k_chunk_end, dim3(n_lat), dim3(64), 0, s, descs, states, fin_partials, fin_off, k);
     return hipGetLastError();
 }
 

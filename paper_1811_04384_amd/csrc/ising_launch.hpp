@@ -73,18 +73,22 @@ hipError_t launch_pack(const uint8_t* in, const Geometry& g, uint64_t* W, hipStr
 // ---- batches --------------------------------------------------------------
 
 // Tiled half-sweep over a wave table covering many lattices.  off32: every
-// listed lattice is smaller than 4 GiB (32-bit word offsets).
-hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, const LatticeState* states,
+// listed lattice is smaller than 4 GiB (32-bit word offsets).  partials
+// (colour 1 of a measured sweep): each wavefront stores its sums there.
+// fin_partials: before its own work, the launch finalizes every tiled
+// lattice's measured sweep fin_off from those partials (written by an
+// earlier launch on the same stream).  Lattices whose sweep_limit is <= an
+// offset took no part in that sweep and are skipped.
+hipError_t launch_halfsweep_multi(int wpt, int block, const LatticeDesc* descs, LatticeState* states,
                                   const WaveItem* waves, int64_t n_waves, int colour, uint32_t sweep_off,
-                                  Partial* partials, bool off32, hipStream_t s);
+                                  Partial* partials, const Partial* fin_partials, uint32_t fin_off, bool off32,
+                                  hipStream_t s);
 inline bool fits_off32(const Geometry& g) { return (uint64_t)g.N * (uint64_t)g.L * 8u < (1ull << 32); }
-// Per-lattice finalize of a measured sweep for the tiled lattices.
-// Lattices whose sweep_limit is <= sweep_off took no part in that sweep and
-// are skipped.
-hipError_t launch_finalize_multi(const LatticeDesc* descs, LatticeState* states, int32_t n_lat,
-                                 const Partial* partials, uint32_t sweep_off, hipStream_t s);
-// t += min(k, sweep_limit) for every lattice.
-hipError_t launch_advance(const LatticeDesc* descs, LatticeState* states, int32_t n_lat, uint32_t k, hipStream_t s);
+// End of a chunk of k sweeps: finalize the tiled lattices' measured sweep
+// fin_off (fin_partials non-null) and advance every lattice's sweep counter
+// by min(k, sweep_limit).
+hipError_t launch_chunk_end(const LatticeDesc* descs, LatticeState* states, int32_t n_lat,
+                            const Partial* fin_partials, uint32_t fin_off, uint32_t k, hipStream_t s);
 // One workgroup per listed lattice, K sweeps per launch; samples after local
 // sweeps s with (s + 1) % every == 0 (every > 0).  lds_bytes > 0 keeps the
 // lattice in LDS (it must fit; call set_resident_lds first, outside any

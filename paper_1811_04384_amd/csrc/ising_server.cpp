@@ -256,12 +256,12 @@ int enqueue_quantum(ising_server* s) {
         }
         for (int32_t k = 0; k < K && n_waves; ++k) {
             ISING_HIP(launch_halfsweep_multi(kServerWpt, block, s->d_desc, s->d_state, s->d_waves, n_waves, 0,
-                                             (uint32_t)k, nullptr, off32, s->stream));
+                                             (uint32_t)k, nullptr, nullptr, 0, off32, s->stream));
             ISING_HIP(launch_halfsweep_multi(kServerWpt, block, s->d_desc, s->d_state, s->d_waves, n_waves, 1,
-                                             (uint32_t)k, nullptr, off32, s->stream));
+                                             (uint32_t)k, nullptr, nullptr, 0, off32, s->stream));
         }
         if (n_res) ISING_HIP(hipStreamWaitEvent(s->stream, s->join_ev, 0));
-        ISING_HIP(launch_advance(s->d_desc, s->d_state, slots, (uint32_t)K, s->stream));
+        ISING_HIP(launch_chunk_end(s->d_desc, s->d_state, slots, nullptr, 0, (uint32_t)K, s->stream));
     }
     ISING_HIP(hipEventRecord(st.done, s->stream));
     st.used = true;
