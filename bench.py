@@ -482,6 +482,9 @@ def main():
     ap.add_argument("--serving-quantum", type=int, default=100)
     ap.add_argument("--serving-slots", type=int, default=128,
                     help="requests resident at once (the rest wait in FIFO order)")
+    ap.add_argument("--valu-rates", action="store_true",
+                    help="only run the instruction-rate microbenchmark (cycles per wave64 instruction of the "
+                         "vector instructions the half-sweep uses) and print its JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run 10 device-to-device copies of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -491,6 +494,21 @@ def main():
         print("bench.py measures one GPU only: the lattice kernels run on a single MI355X and this build has no "
               "multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
         sys.exit(2)
+
+    if args.valu_rates:  # a child process of its own, started before this one touches the GPU
+        import subprocess
+
+        prog = os.path.join(ROOT, "paper_1811_04384_amd", "valu_rates")
+        if not os.path.exists(prog):
+            print(f"{prog} is not built (python -m paper_1811_04384_amd.build)", file=sys.stderr)
+            sys.exit(1)
+        r = subprocess.run([prog], capture_output=True, text=True, timeout=300)
+        log(r.stdout + r.stderr)
+        lines = [x for x in r.stdout.splitlines() if x.startswith("{")]
+        if r.returncode != 0 or not lines:
+            sys.exit(r.returncode or 1)
+        print(lines[-1], flush=True)
+        return
 
     import torch
 

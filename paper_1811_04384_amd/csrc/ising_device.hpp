@@ -73,9 +73,48 @@ __device__ __forceinline__ uint64_t live_mask(int I, int L, int N) {
     return kSpinBits & (~0ull << (3 * (21 - n_live)));
 }
 
-// Up neighbour word of word (I, J): row I-1, or for I = 0 the last word row
-// shifted one field down (position p takes position p-1 of row N-1) with
-// position 0 taken from the word holding row L-1 (row I*, slot sh_star/3).
+// The raw neighbourhood of word (I, J), loaded before any arithmetic needs it
+// so that the random numbers are drawn while the loads are in flight:
+// the word, its left and right words (columns wrap), the words above and
+// below (rows wrap: row N-1 above row 0, row 0 below row N-1), and the
+// patch word of the two wrap rows (row I* for I = 0, row 0 for I = I*;
+// I* = (L-1) mod N is odd, so never 0).  fix_up / fix_down finish the
+// vertical neighbours.
+struct Nbhd {
+    uint64_t w, lf, rt, up, dn, patch;
+};
+
+template <class Load>
+__device__ __forceinline__ Nbhd load_nbhd(const Load& ld, int I, int J, int L, int N, int istar) {
+    Nbhd n;
+    n.w = ld(I, J);
+    n.lf = ld(I, J == 0 ? L - 1 : J - 1);
+    n.rt = ld(I, J == L - 1 ? 0 : J + 1);
+    n.up = ld(I > 0 ? I - 1 : N - 1, J);
+    n.dn = ld(I < N - 1 ? I + 1 : 0, J);
+    n.patch = (I == 0) ? ld(istar, J) : (I == istar) ? ld(0, J) : 0ull;
+    return n;
+}
+
+// Up neighbour word: row I-1, or for I = 0 the last word row shifted one
+// field down (position p takes position p-1 of row N-1) with position 0
+// taken from the word holding row L-1 (row I*, slot sh_star/3).
+__device__ __forceinline__ uint64_t fix_up(const Nbhd& n, int I, int sh_star) {
+    if (I > 0) return n.up;
+    return (n.up >> 3) | (((n.patch >> sh_star) & 1ull) << 60);
+}
+
+// Down neighbour word: row I+1, or for I = N-1 the first word row shifted
+// one field up (position p takes position p+1 of row 0); in word row I* the
+// slot of row L-1 takes row 0 (position 0 of word row 0).
+__device__ __forceinline__ uint64_t fix_down(const Nbhd& n, int I, int N, int istar, int sh_star) {
+    uint64_t d = (I < N - 1) ? n.dn : ((n.dn << 3) & kLow63);
+    if (I == istar) d = (d & ~(1ull << sh_star)) | (((n.patch >> 60) & 1ull) << sh_star);
+    return d;
+}
+
+// The same vertical neighbours loaded and finished in one step, for code
+// that visits a word at a time (strips, observables).
 template <class Load>
 __device__ __forceinline__ uint64_t up_word(const Load& ld, int I, int J, int N, int istar, int sh_star) {
     if (I > 0) return ld(I - 1, J);
@@ -84,9 +123,6 @@ __device__ __forceinline__ uint64_t up_word(const Load& ld, int I, int J, int N,
     return (last >> 3) | (((wrap >> sh_star) & 1ull) << 60);
 }
 
-// Down neighbour word of word (I, J): row I+1, or for I = N-1 the first word
-// row shifted one field up (position p takes position p+1 of row 0); in word
-// row I* the slot of row L-1 takes row 0 (position 0 of word row 0).
 template <class Load>
 __device__ __forceinline__ uint64_t down_word(const Load& ld, int I, int J, int N, int istar, int sh_star) {
     uint64_t d = (I < N - 1) ? ld(I + 1, J) : ((ld(0, J) << 3) & kLow63);
@@ -265,15 +301,29 @@ __device__ __forceinline__ void update_segment(const Load& ld, const Store& st, 
         }
     }
 
+    // every word's neighbourhood is loaded first (a thread's words and their
+    // neighbourhoods are disjoint from the words it stores); with one word
+    // per thread the neighbours are finished at once instead
+    Nbhd nb[WPT];
 #pragma unroll
     for (int k = 0; k < WPT; ++k) {
         const int J = J0 + 2 * k;
         if (J >= L) break;
-        const uint64_t w = ld(I, J);
-        const uint64_t lf = ld(I, J == 0 ? L - 1 : J - 1);
-        const uint64_t rt = ld(I, J == L - 1 ? 0 : J + 1);
-        const uint64_t up = up_word(ld, I, J, N, a.istar, a.sh_star);
-        const uint64_t dn = down_word(ld, I, J, N, a.istar, a.sh_star);
+        if constexpr (WPT == 1) {
+            nb[k].w = ld(I, J);
+            nb[k].lf = ld(I, J == 0 ? L - 1 : J - 1);
+            nb[k].rt = ld(I, J == L - 1 ? 0 : J + 1);
+            nb[k].up = up_word(ld, I, J, N, a.istar, a.sh_star);
+            nb[k].dn = down_word(ld, I, J, N, a.istar, a.sh_star);
+        } else {
+            nb[k] = load_nbhd(ld, I, J, L, N, a.istar);
+        }
+    }
+
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+        const int J = J0 + 2 * k;
+        if (J >= L) break;
 
         Codes codes = {0u, 0u, 0u};
 #pragma unroll
@@ -292,6 +342,9 @@ __device__ __forceinline__ void update_segment(const Load& ld, const Store& st, 
         }
         append_draw(codes, 20, u5[k], a.t4, a.t8);  // dead slot when n_live < 21
 
+        const uint64_t w = nb[k].w, lf = nb[k].lf, rt = nb[k].rt;
+        const uint64_t up = WPT == 1 ? nb[k].up : fix_up(nb[k], I, a.sh_star);
+        const uint64_t dn = WPT == 1 ? nb[k].dn : fix_down(nb[k], I, N, a.istar, a.sh_star);
         const uint64_t f = flip_mask(w, up, dn, lf, rt, assemble_codes(codes), live);
         const uint64_t nw = w ^ f;
         st(I, J, nw);

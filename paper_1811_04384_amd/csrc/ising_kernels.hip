@@ -66,13 +66,17 @@ __global__ void __launch_bounds__(256) k_init(uint64_t* __restrict__ W, Geometry
 // take directly (scalar base + 32-bit vector offset).
 template <bool OFF32>
 struct WordPtr {
+    // global address space: word pointers read from a descriptor would
+    // otherwise be generic, and generic (flat) accesses also wait on the
+    // scalar-load counter
+    using GlobalWord = __attribute__((address_space(1))) uint64_t;
     uint64_t* __restrict__ W;
     uint32_t L;
-    __device__ __forceinline__ uint64_t* at(int i, int j) const {
+    __device__ __forceinline__ GlobalWord* at(int i, int j) const {
+        GlobalWord* g = (GlobalWord*)W;
         if (OFF32)
-            return reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(W) +
-                                               (((uint32_t)i * L + (uint32_t)j) << 3));
-        return W + ((size_t)i * L + (size_t)j);
+            return (GlobalWord*)((__attribute__((address_space(1))) char*)g + (((uint32_t)i * L + (uint32_t)j) << 3));
+        return g + ((size_t)i * L + (size_t)j);
     }
 };
 

@@ -1,0 +1,166 @@
+// Issue cost of the vector instructions the half-sweep kernels are made of,
+// measured on the device this runs on: cycles per wave64 instruction per
+// SIMD, with every SIMD holding 8 wavefronts and every wavefront running 16
+// independent chains of one instruction (so neither latency nor dependence
+// limits the rate).  Each instruction is written in inline assembly, so the
+// loop holds exactly the instructions counted; all of it is register-only
+// vector ALU work, and each thread stores one word of its chains at the end.
+//
+// Back-to-back v_mad_u64_u32 of one wavefront that write the same carry
+// register get a one-cycle s_nop between them from the compiler; the other
+// seven wavefronts of the SIMD issue meanwhile, so the figure is still the
+// vector unit's rate.
+//
+// Output: one line per instruction, then one JSON line with the same
+// figures.  Cycles assume the nominal shader clock reported by the runtime;
+// the ratios to v_add_u32 do not depend on the clock.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+namespace {
+
+constexpr int kIters = 2048;   // loop trips; 16 instructions per trip and wavefront
+constexpr int kWavesPerSimd = 8;
+constexpr int kBlock = 256;
+
+#define VR_CHECK(x)                                                                         \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) {                                                             \
+            std::fprintf(stderr, "HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+            return 1;                                                                       \
+        }                                                                                   \
+    } while (0)
+
+#define VR_16(OP) OP(a0) OP(a1) OP(a2) OP(a3) OP(a4) OP(a5) OP(a6) OP(a7) \
+                  OP(a8) OP(a9) OP(a10) OP(a11) OP(a12) OP(a13) OP(a14) OP(a15)
+
+// One lane-mask / carry SGPR pair per chain (s_a0 .. s_a15), so consecutive
+// instructions never write the same scalar register.
+#define VR_SGPRS                                                                                      \
+    uint64_t s_a0 = 0, s_a1 = 0, s_a2 = 0, s_a3 = 0, s_a4 = 0, s_a5 = 0, s_a6 = 0, s_a7 = 0, s_a8 = 0, \
+             s_a9 = 0, s_a10 = 0, s_a11 = 0, s_a12 = 0, s_a13 = 0, s_a14 = 0, s_a15 = 0;
+#define VR_SGPR_XOR                                                                                   \
+    s_a0 ^ s_a1 ^ s_a2 ^ s_a3 ^ s_a4 ^ s_a5 ^ s_a6 ^ s_a7 ^ s_a8 ^ s_a9 ^ s_a10 ^ s_a11 ^ s_a12 ^ s_a13 ^ \
+        s_a14 ^ s_a15
+
+// 32-bit chains: a_i = OP(a_i, b, k)
+#define VR_KERNEL32(NAME, ASM_OP)                                                                     \
+    __global__ void __launch_bounds__(kBlock) NAME(uint32_t* out, uint32_t k, uint64_t mask) {        \
+        const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;                                  \
+        uint32_t a0 = tid, a1 = tid + 1, a2 = tid + 2, a3 = tid + 3, a4 = tid + 4, a5 = tid + 5,     \
+                 a6 = tid + 6, a7 = tid + 7, a8 = tid + 8, a9 = tid + 9, a10 = tid + 10, a11 = tid + 11, \
+                 a12 = tid + 12, a13 = tid + 13, a14 = tid + 14, a15 = tid + 15;                     \
+        const uint32_t b = tid * 0x9E3779B9u;                                                        \
+        VR_SGPRS                                                                                     \
+        for (int it = 0; it < kIters; ++it) { VR_16(ASM_OP) }                                        \
+        out[tid] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7 ^ a8 ^ a9 ^ a10 ^ a11 ^ a12 ^ a13 ^ a14 ^ a15 ^ \
+                   (uint32_t)(VR_SGPR_XOR);                                                          \
+    }
+
+#define OP_ADD(a) asm volatile("v_add_u32_e32 %0, %1, %0" : "+v"(a) : "s"(k));
+#define OP_XOR3(a) asm volatile("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(a) : "v"(b), "s"(k));
+#define OP_LSHLOR(a) asm volatile("v_lshl_or_b32 %0, %0, 3, %1" : "+v"(a) : "v"(b));
+#define OP_LSHR(a) asm volatile("v_lshrrev_b32_e32 %0, 3, %0" : "+v"(a));
+#define OP_CNDMASK(a) asm volatile("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(a) : "v"(b), "s"(mask));
+#define OP_MULHI(a) asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(a) : "s"(k));
+#define OP_MULLO(a) asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(a) : "s"(k));
+// compare into a lane mask (its own SGPR pair per chain, read at the end),
+// then one add to move the chain on
+#define OP_CMP(a)                                                                       \
+    {                                                                                   \
+        asm volatile("v_cmp_gt_u32_e64 %0, %1, %2" : "=s"(s_##a) : "s"(k), "v"(a));     \
+        asm volatile("v_add_u32_e32 %0, 1, %0" : "+v"(a));                              \
+    }
+
+VR_KERNEL32(k_add, OP_ADD)
+VR_KERNEL32(k_xor3, OP_XOR3)
+VR_KERNEL32(k_lshl_or, OP_LSHLOR)
+VR_KERNEL32(k_lshr, OP_LSHR)
+VR_KERNEL32(k_cndmask, OP_CNDMASK)
+VR_KERNEL32(k_mul_hi, OP_MULHI)
+VR_KERNEL32(k_mul_lo, OP_MULLO)
+VR_KERNEL32(k_cmp_add, OP_CMP)
+
+// 64-bit chains through the addend: a_i = b * k + a_i (v_mad_u64_u32), or a
+// 64-bit shift.
+#define VR_KERNEL64(NAME, ASM_OP)                                                                     \
+    __global__ void __launch_bounds__(kBlock) NAME(uint32_t* out, uint32_t k, uint64_t mask) {        \
+        const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;                                  \
+        uint64_t a0 = tid + mask, a1 = a0 + 1, a2 = a0 + 2, a3 = a0 + 3, a4 = a0 + 4, a5 = a0 + 5,   \
+                 a6 = a0 + 6, a7 = a0 + 7, a8 = a0 + 8, a9 = a0 + 9, a10 = a0 + 10, a11 = a0 + 11,   \
+                 a12 = a0 + 12, a13 = a0 + 13, a14 = a0 + 14, a15 = a0 + 15;                         \
+        const uint32_t b = tid * 0x9E3779B9u;                                                        \
+        VR_SGPRS                                                                                     \
+        for (int it = 0; it < kIters; ++it) { VR_16(ASM_OP) }                                        \
+        const uint64_t r = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7 ^ a8 ^ a9 ^ a10 ^ a11 ^ a12 ^ a13 ^ a14 ^ a15 ^ \
+                           (VR_SGPR_XOR);                                                            \
+        out[tid] = (uint32_t)r ^ (uint32_t)(r >> 32);                                                \
+    }
+
+#define OP_MAD64(a) asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(a), "=s"(s_##a) : "v"(b), "s"(k));
+#define OP_SHL64(a) asm volatile("v_lshlrev_b64 %0, 3, %0" : "+v"(a));
+
+VR_KERNEL64(k_mad_u64, OP_MAD64)
+VR_KERNEL64(k_lshl_b64, OP_SHL64)
+
+typedef void (*Kernel)(uint32_t*, uint32_t, uint64_t);
+
+struct Case {
+    const char* name;
+    Kernel fn;
+    int instr_per_op;  // vector instructions per chain step
+};
+
+}  // namespace
+
+int main() {
+    hipDeviceProp_t prop;
+    VR_CHECK(hipGetDeviceProperties(&prop, 0));
+    const int cus = prop.multiProcessorCount;
+    const double clock_hz = (double)prop.clockRate * 1e3;
+    const int simds = cus * 4;
+    const int grid = simds * kWavesPerSimd * 64 / kBlock;
+    uint32_t* out = nullptr;
+    VR_CHECK(hipMalloc(&out, sizeof(uint32_t) * (size_t)grid * kBlock));
+    hipEvent_t t0, t1;
+    VR_CHECK(hipEventCreate(&t0));
+    VR_CHECK(hipEventCreate(&t1));
+    const Case cases[] = {
+        {"v_add_u32", k_add, 1},           {"v_bitop3_b32", k_xor3, 1},
+        {"v_lshl_or_b32", k_lshl_or, 1},   {"v_lshrrev_b32", k_lshr, 1},
+        {"v_cndmask_b32_e64", k_cndmask, 1}, {"v_cmp_gt_u32_e64+v_add_u32", k_cmp_add, 2},
+        {"v_mul_hi_u32", k_mul_hi, 1},     {"v_mul_lo_u32", k_mul_lo, 1},
+        {"v_mad_u64_u32", k_mad_u64, 1},   {"v_lshlrev_b64", k_lshl_b64, 1},
+    };
+    const int n_cases = (int)(sizeof cases / sizeof cases[0]);
+    double cyc[16];
+    std::printf("device %s (%s), %d CUs, nominal clock %.0f MHz, %d wavefronts per SIMD\n", prop.name,
+                prop.gcnArchName, cus, clock_hz / 1e6, kWavesPerSimd);
+    for (int c = 0; c < n_cases; ++c) {
+        hipLaunchKernelGGL(cases[c].fn, dim3(grid), dim3(kBlock), 0, 0, out, 0x9E3779B9u, 0x5555555555555555ull);
+        VR_CHECK(hipGetLastError());
+        VR_CHECK(hipDeviceSynchronize());
+        const int reps = 5;
+        VR_CHECK(hipEventRecord(t0, 0));
+        for (int r = 0; r < reps; ++r)
+            hipLaunchKernelGGL(cases[c].fn, dim3(grid), dim3(kBlock), 0, 0, out, 0x9E3779B9u, 0x5555555555555555ull);
+        VR_CHECK(hipGetLastError());
+        VR_CHECK(hipEventRecord(t1, 0));
+        VR_CHECK(hipEventSynchronize(t1));
+        float ms = 0.f;
+        VR_CHECK(hipEventElapsedTime(&ms, t0, t1));
+        ms /= reps;
+        const double instr_per_simd = (double)kWavesPerSimd * kIters * 16 * cases[c].instr_per_op;
+        cyc[c] = ms * 1e-3 * clock_hz / instr_per_simd;
+        std::printf("%-30s %8.3f ms  %5.2f cycles per wave64 instruction\n", cases[c].name, ms, cyc[c]);
+    }
+    std::printf("{\"probe\": \"valu_rates\", \"arch\": \"%s\", \"cus\": %d, \"clock_mhz\": %.0f, \"cycles\": {", prop.gcnArchName,
+                cus, clock_hz / 1e6);
+    for (int c = 0; c < n_cases; ++c) std::printf("%s\"%s\": %.3f", c ? ", " : "", cases[c].name, cyc[c]);
+    std::printf("}}\n");
+    VR_CHECK(hipFree(out));
+    return 0;
+}
