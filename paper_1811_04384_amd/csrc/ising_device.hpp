@@ -34,14 +34,43 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
+// A vector-register copy of a wave-uniform value.  On gfx950, simple 32-bit
+// vector instructions (add, xor, three-input bitwise) that read a scalar
+// register take about 4.4 cycles per wave64 instruction when they follow
+// each other, against about 2.6 when all operands are vector registers or
+// constants (the instruction-rate microbenchmark, valu_rates.hip); the
+// Philox rounds therefore read their round keys from vector registers.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t s) {
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
 // Philox4x32-10 (Salmon et al., SC'11) for the counter shape used by every
 // draw of this library: words 0, 2, 3 of the counter and the key are the same
 // for all lanes of a wavefront, only word 1 differs.  Rounds 1-3 are written
 // with plain XORs so the compiler keeps their wave-uniform parts on the
 // scalar unit (round 1 is entirely scalar, rounds 2 and 3 need one 64-bit
-// product each); rounds 4-10 use the three-input XOR.
-__device__ __forceinline__ U4 philox_lane_c1(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                             uint32_t k1) {
+// product each); rounds 4-10 use the three-input XOR.  With RK, the round
+// keys that the three-input XORs of rounds 4-10 read come from vector
+// registers (RoundKeys, computed once per thread).
+struct RoundKeys {
+    uint32_t k0[7], k1[7];  // keys of rounds 4..10
+};
+
+__device__ __forceinline__ RoundKeys round_keys(uint32_t k0, uint32_t k1) {
+    RoundKeys rk;
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+        rk.k0[r - 3] = in_vgpr(k0 + (uint32_t)r * kPhiloxW0);
+        rk.k1[r - 3] = in_vgpr(k1 + (uint32_t)r * kPhiloxW1);
+    }
+    return rk;
+}
+
+template <bool RK>
+__device__ __forceinline__ U4 philox_rounds(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                            uint32_t k1, const RoundKeys* rk) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)kPhiloxM0 * c0;
@@ -51,11 +80,11 @@ __device__ __forceinline__ U4 philox_lane_c1(uint32_t c0, uint32_t c1, uint32_t 
             n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
             n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
         } else if (r == 3) {  // word 3 is still wave-uniform: c3 ^ k1 on the scalar unit
-            n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+            n0 = xor3((uint32_t)(pb >> 32), c1, RK ? rk->k0[0] : k0);
             n2 = (uint32_t)(pa >> 32) ^ (c3 ^ k1);
         } else {
-            n0 = xor3((uint32_t)(pb >> 32), c1, k0);
-            n2 = xor3((uint32_t)(pa >> 32), c3, k1);
+            n0 = xor3((uint32_t)(pb >> 32), c1, RK ? rk->k0[r - 3] : k0);
+            n2 = xor3((uint32_t)(pa >> 32), c3, RK ? rk->k1[r - 3] : k1);
         }
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
@@ -65,6 +94,18 @@ __device__ __forceinline__ U4 philox_lane_c1(uint32_t c0, uint32_t c1, uint32_t 
         k1 += kPhiloxW1;
     }
     return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 philox_lane_c1(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                             uint32_t k1) {
+    return philox_rounds<false>(c0, c1, c2, c3, k0, k1, nullptr);
+}
+
+// The same block with the keys of rounds 4-10 taken from rk (which must hold
+// round_keys(k0, k1)).
+__device__ __forceinline__ U4 philox_lane_c1(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                             uint32_t k1, const RoundKeys& rk) {
+    return philox_rounds<true>(c0, c1, c2, c3, k0, k1, &rk);
 }
 
 // Live-spin mask of word row I: positions p with I + pN < L.
@@ -280,12 +321,13 @@ __device__ __forceinline__ void update_segment(const Load& ld, const Store& st, 
     const int n_live = min(21, (L - 1 - I) / N + 1);
     const uint64_t live = kSpinBits & (~0ull << (3 * (21 - n_live)));
     const uint32_t row_base = (uint32_t)I * (uint32_t)L;
+    const RoundKeys rk = round_keys(a.k0, a.k1);
 
     // position-20 draws of the segment's words, word k's draw in u5[k]
     uint32_t u5[4] = {0u, 0u, 0u, 0u};
     if (n_live == 21) {
         const uint32_t col = ((uint32_t)J0 & ~7u) | ((uint32_t)J0 & 1u);
-        const U4 r = philox_lane_c1(a.t_lo, row_base + col, a.t_hi, 5u | (1u << 3), a.k0, a.k1);
+        const U4 r = philox_lane_c1(a.t_lo, row_base + col, a.t_hi, 5u | (1u << 3), a.k0, a.k1, rk);
         if (WPT == 4) {  // segments are 8-aligned: output k belongs to word k
             u5[0] = r.x;
             u5[1] = r.y;
@@ -330,7 +372,7 @@ __device__ __forceinline__ void update_segment(const Load& ld, const Store& st, 
         for (int g = 0; g < 5; ++g) {
             if (4 * g < n_live) {
                 const U4 r =
-                    philox_lane_c1(a.t_lo, row_base + (uint32_t)J, a.t_hi, (uint32_t)g | (1u << 3), a.k0, a.k1);
+                    philox_lane_c1(a.t_lo, row_base + (uint32_t)J, a.t_hi, (uint32_t)g | (1u << 3), a.k0, a.k1, rk);
                 append_draw(codes, 4 * g + 0, r.x, a.t4, a.t8);
                 append_draw(codes, 4 * g + 1, r.y, a.t4, a.t8);
                 append_draw(codes, 4 * g + 2, r.z, a.t4, a.t8);

@@ -65,10 +65,11 @@ __global__ void __launch_bounds__(256) k_replica_halfsweep(uint64_t* __restrict_
     const uint64_t* __restrict__ row_up = W + (size_t)ru * (size_t)L;
     const uint64_t* __restrict__ row_dn = W + (size_t)rd * (size_t)L;
 
+    const RoundKeys rk = round_keys(a.k0, a.k1);
     uint32_t u20[4] = {0u, 0u, 0u, 0u};
     {
         const uint32_t col = ((uint32_t)J0 & ~7u) | ((uint32_t)J0 & 1u);
-        const U4 o = philox_lane_c1(a.t_lo, row_base + col, a.t_hi, 5u + c3, a.k0, a.k1);
+        const U4 o = philox_lane_c1(a.t_lo, row_base + col, a.t_hi, 5u + c3, a.k0, a.k1, rk);
         const uint32_t q0 = ((uint32_t)J0 >> 1) & 3u;
 #pragma unroll
         for (int k = 0; k < WPT; ++k) {
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(256) k_replica_halfsweep(uint64_t* __restrict_
         Codes codes = {0u, 0u, 0u};
 #pragma unroll
         for (int g = 0; g < 5; ++g) {
-            const U4 o = philox_lane_c1(a.t_lo, row_base + (uint32_t)J, a.t_hi, (uint32_t)g + c3, a.k0, a.k1);
+            const U4 o = philox_lane_c1(a.t_lo, row_base + (uint32_t)J, a.t_hi, (uint32_t)g + c3, a.k0, a.k1, rk);
             append_draw(codes, 4 * g + 0, o.x, a.t4[4 * g + 0], a.t8[4 * g + 0]);
             append_draw(codes, 4 * g + 1, o.y, a.t4[4 * g + 1], a.t8[4 * g + 1]);
             append_draw(codes, 4 * g + 2, o.z, a.t4[4 * g + 2], a.t8[4 * g + 2]);

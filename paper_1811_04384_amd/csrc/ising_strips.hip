@@ -32,6 +32,7 @@ __global__ void __launch_bounds__(64) k_strip_phase(uint64_t* __restrict__ W, St
     const uint32_t c3_pick = 8u * (2u + a.phase) + (a.t_hi << 8);
     const uint32_t c3_word = 8u * (4u + a.phase) + (a.t_hi << 8);
     const int col0 = p * a.S + a.off;
+    const RoundKeys rk = round_keys(a.k0, a.k1);
     U4 pick = {0u, 0u, 0u, 0u};
     for (uint32_t k = 0; k < a.picks; ++k) {
         if ((k & 1u) == 0u) pick = philox_lane_c1(a.t_lo, (uint32_t)p, k >> 1, c3_pick, a.k0, a.k1);
@@ -49,13 +50,13 @@ __global__ void __launch_bounds__(64) k_strip_phase(uint64_t* __restrict__ W, St
         Codes codes = {0u, 0u, 0u};
 #pragma unroll
         for (int g = 0; g < 5; ++g) {
-            const U4 r = philox_lane_c1(a.t_lo, (uint32_t)p, k, (uint32_t)g + c3_word, a.k0, a.k1);
+            const U4 r = philox_lane_c1(a.t_lo, (uint32_t)p, k, (uint32_t)g + c3_word, a.k0, a.k1, rk);
             append_draw(codes, 4 * g + 0, r.x, a.t4, a.t8);
             append_draw(codes, 4 * g + 1, r.y, a.t4, a.t8);
             append_draw(codes, 4 * g + 2, r.z, a.t4, a.t8);
             append_draw(codes, 4 * g + 3, r.w, a.t4, a.t8);
         }
-        const U4 r5 = philox_lane_c1(a.t_lo, (uint32_t)p, k, 5u + c3_word, a.k0, a.k1);
+        const U4 r5 = philox_lane_c1(a.t_lo, (uint32_t)p, k, 5u + c3_word, a.k0, a.k1, rk);
         append_draw(codes, 20, r5.x, a.t4, a.t8);
         const uint64_t f = flip_mask(w, up, dn, lf, rt, assemble_codes(codes), live_mask(I, L, N));
         W[(size_t)I * (size_t)L + (size_t)J] = w ^ f;
@@ -84,16 +85,17 @@ __global__ void __launch_bounds__(256) k_strip_draws(StripArgs a, uint32_t k0, u
     const uint32_t y = (k & 1u) ? pick.w : pick.y;
     const uint32_t I = (uint32_t)(((uint64_t)x * (uint64_t)(uint32_t)a.N) >> 32);
     const uint32_t jl = (uint32_t)(((uint64_t)y * (uint64_t)(uint32_t)a.width) >> 32);
+    const RoundKeys rk = round_keys(a.k0, a.k1);
     Codes codes = {0u, 0u, 0u};
 #pragma unroll
     for (int g = 0; g < 5; ++g) {
-        const U4 r = philox_lane_c1(a.t_lo, p, k, (uint32_t)g + c3_word, a.k0, a.k1);
+        const U4 r = philox_lane_c1(a.t_lo, p, k, (uint32_t)g + c3_word, a.k0, a.k1, rk);
         append_draw(codes, 4 * g + 0, r.x, a.t4, a.t8);
         append_draw(codes, 4 * g + 1, r.y, a.t4, a.t8);
         append_draw(codes, 4 * g + 2, r.z, a.t4, a.t8);
         append_draw(codes, 4 * g + 3, r.w, a.t4, a.t8);
     }
-    const U4 r5 = philox_lane_c1(a.t_lo, p, k, 5u + c3_word, a.k0, a.k1);
+    const U4 r5 = philox_lane_c1(a.t_lo, p, k, 5u + c3_word, a.k0, a.k1, rk);
     append_draw(codes, 20, r5.x, a.t4, a.t8);
     pos[i] = (I << kStripColBits) | jl;
     codes_out[i] = assemble_codes(codes);

@@ -11,6 +11,12 @@
 // seven wavefronts of the SIMD issue meanwhile, so the figure is still the
 // vector unit's rate.
 //
+// The rates do not add up in mixed code: an instruction that reads a scalar
+// register is slow when such instructions follow each other, and nearly as
+// fast as the all-vector forms when they alternate with them (the
+// "alternating" cases), so a kernel's time is measured, not predicted, from
+// these figures.
+//
 // Output: one line per instruction, then one JSON line with the same
 // figures.  Cycles assume the nominal shader clock reported by the runtime;
 // the ratios to v_add_u32 do not depend on the clock.
@@ -54,6 +60,8 @@ constexpr int kBlock = 256;
                  a6 = tid + 6, a7 = tid + 7, a8 = tid + 8, a9 = tid + 9, a10 = tid + 10, a11 = tid + 11, \
                  a12 = tid + 12, a13 = tid + 13, a14 = tid + 14, a15 = tid + 15;                     \
         const uint32_t b = tid * 0x9E3779B9u;                                                        \
+        const uint32_t vk = k ^ (tid & 1u); /* the constant, in a vector register */                 \
+        const uint32_t v3 = 3u + (tid >> 31); /* a shift amount (3), in a vector register */         \
         VR_SGPRS                                                                                     \
         for (int it = 0; it < kIters; ++it) { VR_16(ASM_OP) }                                        \
         out[tid] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7 ^ a8 ^ a9 ^ a10 ^ a11 ^ a12 ^ a13 ^ a14 ^ a15 ^ \
@@ -61,6 +69,22 @@ constexpr int kBlock = 256;
     }
 
 #define OP_ADD(a) asm volatile("v_add_u32_e32 %0, %1, %0" : "+v"(a) : "s"(k));
+#define OP_ADD_V(a) asm volatile("v_add_u32_e32 %0, %1, %0" : "+v"(a) : "v"(b));
+#define OP_ADD_C(a) asm volatile("v_add_u32_e32 %0, 7, %0" : "+v"(a));
+#define OP_XOR3_V(a) asm volatile("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(a) : "v"(b), "v"(vk));
+#define OP_LSHR_S(a) asm volatile("v_lshrrev_b32_e32 %0, %1, %0" : "+v"(a) : "s"(k));
+#define OP_ADD_L(a) asm volatile("v_add_u32_e32 %0, 0x9e3779b9, %0" : "+v"(a));
+#define OP_SUB_V(a) asm volatile("v_sub_u32_e32 %0, %0, %1" : "+v"(a) : "v"(b));
+#define OP_XOR_V(a) asm volatile("v_xor_b32_e32 %0, %1, %0" : "+v"(a) : "v"(b));
+#define OP_XOR3_C(a) asm volatile("v_bitop3_b32 %0, %0, %1, 5 bitop3:0x96" : "+v"(a) : "v"(b));
+#define OP_LSHLOR_V(a) asm volatile("v_lshl_or_b32 %0, %0, %1, %2" : "+v"(a) : "v"(v3), "v"(b));
+#define OP_ALIGN_C(a) asm volatile("v_alignbit_b32 %0, %0, %1, 31" : "+v"(a) : "v"(b));
+#define OP_ALIGN_V(a) asm volatile("v_alignbit_b32 %0, %0, %1, %2" : "+v"(a) : "v"(b), "v"(v3));
+#define OP_CMP_V(a)                                                                     \
+    {                                                                                   \
+        asm volatile("v_cmp_gt_u32_e64 %0, %1, %2" : "=s"(s_##a) : "v"(vk), "v"(a));    \
+        asm volatile("v_add_u32_e32 %0, 1, %0" : "+v"(a));                              \
+    }
 #define OP_XOR3(a) asm volatile("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(a) : "v"(b), "s"(k));
 #define OP_LSHLOR(a) asm volatile("v_lshl_or_b32 %0, %0, 3, %1" : "+v"(a) : "v"(b));
 #define OP_LSHR(a) asm volatile("v_lshrrev_b32_e32 %0, 3, %0" : "+v"(a));
@@ -75,7 +99,54 @@ constexpr int kBlock = 256;
         asm volatile("v_add_u32_e32 %0, 1, %0" : "+v"(a));                              \
     }
 
+// Dependent variants: all 16 instructions of a trip on one chain.
+#define VR_DEP16(OP) OP(a0) OP(a0) OP(a0) OP(a0) OP(a0) OP(a0) OP(a0) OP(a0) \
+                     OP(a0) OP(a0) OP(a0) OP(a0) OP(a0) OP(a0) OP(a0) OP(a0)
+#define OP_ADD_V_DEP(a) VR_DEP16(OP_ADD_V)
+#define OP_XOR3_V_DEP(a) VR_DEP16(OP_XOR3_V)
+#define OP_XOR3_S_DEP(a) VR_DEP16(OP_XOR3)
+#define OP_ADD_V_PAIR(a) OP_ADD_V(a0) OP_ADD_V(a1) OP_ADD_V(a0) OP_ADD_V(a1) OP_ADD_V(a0) OP_ADD_V(a1) \
+    OP_ADD_V(a0) OP_ADD_V(a1) OP_ADD_V(a0) OP_ADD_V(a1) OP_ADD_V(a0) OP_ADD_V(a1) OP_ADD_V(a0) OP_ADD_V(a1) \
+    OP_ADD_V(a0) OP_ADD_V(a1)
+
 VR_KERNEL32(k_add, OP_ADD)
+VR_KERNEL32(k_add_v, OP_ADD_V)
+VR_KERNEL32(k_add_c, OP_ADD_C)
+VR_KERNEL32(k_xor3_v, OP_XOR3_V)
+VR_KERNEL32(k_lshr_s, OP_LSHR_S)
+VR_KERNEL32(k_add_l, OP_ADD_L)
+VR_KERNEL32(k_sub_v, OP_SUB_V)
+VR_KERNEL32(k_xor_v, OP_XOR_V)
+VR_KERNEL32(k_xor3_c, OP_XOR3_C)
+VR_KERNEL32(k_lshl_or_v, OP_LSHLOR_V)
+VR_KERNEL32(k_align_c, OP_ALIGN_C)
+VR_KERNEL32(k_align_v, OP_ALIGN_V)
+VR_KERNEL32(k_cmp_v, OP_CMP_V)
+
+// 32-bit kernels whose trip is one 16-instruction group given by ASM_GROUP.
+#define VR_KERNEL32G(NAME, ASM_GROUP)                                                                 \
+    __global__ void __launch_bounds__(kBlock) NAME(uint32_t* out, uint32_t k, uint64_t mask) {        \
+        const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;                                  \
+        uint32_t a0 = tid, a1 = tid + 1;                                                             \
+        const uint32_t b = tid * 0x9E3779B9u;                                                        \
+        const uint32_t vk = k ^ (tid & 1u);                                                          \
+        (void)mask;                                                                                  \
+        for (int it = 0; it < kIters; ++it) { ASM_GROUP(a0) }                                        \
+        out[tid] = a0 ^ a1;                                                                          \
+    }
+VR_KERNEL32G(k_add_v_dep, OP_ADD_V_DEP)
+VR_KERNEL32G(k_xor3_v_dep, OP_XOR3_V_DEP)
+VR_KERNEL32G(k_xor3_s_dep, OP_XOR3_S_DEP)
+VR_KERNEL32G(k_add_v_pair, OP_ADD_V_PAIR)
+
+// Mixed: each trip alternates a fast-form instruction (all vector operands)
+// with a slow-form one (a scalar operand), on 16 independent chains.
+#define OP_MIX_XOR3(a) OP_XOR3_V(a) OP_ADD(a)
+#define OP_MIX_MAD(a)                                                                                         \
+    asm volatile("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(a) : "v"(b), "v"(vk));                    \
+    asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(a) : "s"(k));
+VR_KERNEL32(k_mix_xor3_add, OP_MIX_XOR3)
+VR_KERNEL32(k_mix_xor3_mulhi, OP_MIX_MAD)
 VR_KERNEL32(k_xor3, OP_XOR3)
 VR_KERNEL32(k_lshl_or, OP_LSHLOR)
 VR_KERNEL32(k_lshr, OP_LSHR)
@@ -93,6 +164,7 @@ VR_KERNEL32(k_cmp_add, OP_CMP)
                  a6 = a0 + 6, a7 = a0 + 7, a8 = a0 + 8, a9 = a0 + 9, a10 = a0 + 10, a11 = a0 + 11,   \
                  a12 = a0 + 12, a13 = a0 + 13, a14 = a0 + 14, a15 = a0 + 15;                         \
         const uint32_t b = tid * 0x9E3779B9u;                                                        \
+        const uint32_t vk = k ^ (tid & 1u); /* the multiplier, in a vector register */               \
         VR_SGPRS                                                                                     \
         for (int it = 0; it < kIters; ++it) { VR_16(ASM_OP) }                                        \
         const uint64_t r = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7 ^ a8 ^ a9 ^ a10 ^ a11 ^ a12 ^ a13 ^ a14 ^ a15 ^ \
@@ -101,9 +173,11 @@ VR_KERNEL32(k_cmp_add, OP_CMP)
     }
 
 #define OP_MAD64(a) asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(a), "=s"(s_##a) : "v"(b), "s"(k));
+#define OP_MAD64_V(a) asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(a), "=s"(s_##a) : "v"(b), "v"(vk));
 #define OP_SHL64(a) asm volatile("v_lshlrev_b64 %0, 3, %0" : "+v"(a));
 
 VR_KERNEL64(k_mad_u64, OP_MAD64)
+VR_KERNEL64(k_mad_u64_v, OP_MAD64_V)
 VR_KERNEL64(k_lshl_b64, OP_SHL64)
 
 typedef void (*Kernel)(uint32_t*, uint32_t, uint64_t);
@@ -128,15 +202,41 @@ int main() {
     hipEvent_t t0, t1;
     VR_CHECK(hipEventCreate(&t0));
     VR_CHECK(hipEventCreate(&t1));
+    // operands: s = one scalar register, v = vector registers only, c = an
+    // inline constant
     const Case cases[] = {
-        {"v_add_u32", k_add, 1},           {"v_bitop3_b32", k_xor3, 1},
-        {"v_lshl_or_b32", k_lshl_or, 1},   {"v_lshrrev_b32", k_lshr, 1},
-        {"v_cndmask_b32_e64", k_cndmask, 1}, {"v_cmp_gt_u32_e64+v_add_u32", k_cmp_add, 2},
-        {"v_mul_hi_u32", k_mul_hi, 1},     {"v_mul_lo_u32", k_mul_lo, 1},
-        {"v_mad_u64_u32", k_mad_u64, 1},   {"v_lshlrev_b64", k_lshl_b64, 1},
+        {"v_add_u32 (s)", k_add, 1},
+        {"v_add_u32 (v)", k_add_v, 1},
+        {"v_add_u32 (c)", k_add_c, 1},
+        {"v_add_u32 (literal)", k_add_l, 1},
+        {"v_add_u32 (v), one chain", k_add_v_dep, 1},
+        {"v_add_u32 (v), two chains", k_add_v_pair, 1},
+        {"v_sub_u32 (v)", k_sub_v, 1},
+        {"v_xor_b32 (v)", k_xor_v, 1},
+        {"v_bitop3_b32 (s)", k_xor3, 1},
+        {"v_bitop3_b32 (v)", k_xor3_v, 1},
+        {"v_bitop3_b32 (c)", k_xor3_c, 1},
+        {"v_bitop3_b32 (v), one chain", k_xor3_v_dep, 1},
+        {"v_bitop3_b32 (s), one chain", k_xor3_s_dep, 1},
+        {"v_bitop3_b32 (v) / v_add_u32 (s) alternating", k_mix_xor3_add, 2},
+        {"v_bitop3_b32 (v) / v_mul_hi_u32 (s) alternating", k_mix_xor3_mulhi, 2},
+        {"v_lshl_or_b32 (c, v)", k_lshl_or, 1},
+        {"v_lshl_or_b32 (v)", k_lshl_or_v, 1},
+        {"v_alignbit_b32 (c)", k_align_c, 1},
+        {"v_alignbit_b32 (v)", k_align_v, 1},
+        {"v_lshrrev_b32 (c)", k_lshr, 1},
+        {"v_lshrrev_b32 (s)", k_lshr_s, 1},
+        {"v_cndmask_b32_e64 (s mask)", k_cndmask, 1},
+        {"v_cmp_gt_u32_e64 (s) + v_add_u32 (c)", k_cmp_add, 2},
+        {"v_cmp_gt_u32_e64 (v) + v_add_u32 (c)", k_cmp_v, 2},
+        {"v_mul_hi_u32 (s)", k_mul_hi, 1},
+        {"v_mul_lo_u32 (s)", k_mul_lo, 1},
+        {"v_mad_u64_u32 (s)", k_mad_u64, 1},
+        {"v_mad_u64_u32 (v)", k_mad_u64_v, 1},
+        {"v_lshlrev_b64 (c)", k_lshl_b64, 1},
     };
     const int n_cases = (int)(sizeof cases / sizeof cases[0]);
-    double cyc[16];
+    double cyc[32];
     std::printf("device %s (%s), %d CUs, nominal clock %.0f MHz, %d wavefronts per SIMD\n", prop.name,
                 prop.gcnArchName, cus, clock_hz / 1e6, kWavesPerSimd);
     for (int c = 0; c < n_cases; ++c) {
@@ -155,7 +255,7 @@ int main() {
         ms /= reps;
         const double instr_per_simd = (double)kWavesPerSimd * kIters * 16 * cases[c].instr_per_op;
         cyc[c] = ms * 1e-3 * clock_hz / instr_per_simd;
-        std::printf("%-30s %8.3f ms  %5.2f cycles per wave64 instruction\n", cases[c].name, ms, cyc[c]);
+        std::printf("%-48s %8.3f ms  %5.2f cycles per wave64 instruction\n", cases[c].name, ms, cyc[c]);
     }
     std::printf("{\"probe\": \"valu_rates\", \"arch\": \"%s\", \"cus\": %d, \"clock_mhz\": %.0f, \"cycles\": {", prop.gcnArchName,
                 cus, clock_hz / 1e6);
