@@ -40,6 +40,15 @@ def test_library_was_built_from_these_sources():
     assert ising.ising_version().endswith(" src " + source_hash())
 
 
+def test_instruction_rate_microbenchmark_is_built():
+    # built beside the library by the same build step; bench.py --valu-rates runs it
+    from paper_1811_04384_amd.build import VALU_RATES
+
+    assert os.path.isfile(VALU_RATES) and os.access(VALU_RATES, os.X_OK)
+    assert os.path.getmtime(VALU_RATES) >= os.path.getmtime(
+        os.path.join(ROOT, "paper_1811_04384_amd", "csrc", "valu_rates.hip"))
+
+
 def test_geometry_matches_oracle():
     for L in list(range(4, 400, 2)) + [1008, 2016, 4096, 32768, 1 << 18]:
         assert ising.ising_word_rows(L) == oracle.word_rows(L)
