@@ -155,26 +155,46 @@ def load_traffic(plan):
         return None
 
 
-def cpu_baseline(target_s=12.0):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(target_s=12.0, single_s=4.0):
     """The CPU oracle on a bounded sample of the headline workload: a
     4096 x 4096 window of the L = 32768 hot-start lattice (seed 11) evolved
-    at T = 2.269 for as many sweeps as fit in about target_s seconds (the
-    per-site work is the same as on the full lattice)."""
+    at T = 2.269 for as many sweeps as fit in about target_s seconds on all
+    host threads (the per-site work is the same as on the full lattice), and
+    a 1024 x 1024 window on one thread for about single_s seconds."""
     import oracle
 
-    L, seed, T, w = L_MAIN, SEED_MAIN, 2.269, 4096
-    win = oracle.init_window(L, seed, True, 0, 0, w, w)
+    L, seed, T = L_MAIN, SEED_MAIN, 2.269
+
+    def rate(w, threads, budget):
+        win = oracle.init_window(L, seed, True, 0, 0, w, w)
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            oracle.sweep_window(win, L, seed, done, 2, T, 0, 0, threads=threads)
+            done += 2
+        dt = time.perf_counter() - t0
+        return done * (w - 2) * (w - 2) / (dt * 1e9), done, dt  # the window minus its border
+
     threads = oracle.max_threads()
-    done = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < target_s:
-        oracle.sweep_window(win, L, seed, done, 2, T, 0, 0)
-        done += 2
-    dt = time.perf_counter() - t0
-    attempts = done * (w - 2) * (w - 2)  # sites updated per sweep: the window minus its border
-    return {"value": round(attempts / (dt * 1e9), 5), "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": f"{w}x{w} window of the L=32768 hot-start lattice (seed 11), T=2.269, {done} sweeps, "
-                      f"{dt:.1f} s on {threads} threads"}
+    value, done, dt = rate(4096, 0, target_s)
+    single, done1, dt1 = rate(1024, 1, single_s)
+    return {"value": round(value, 5), "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"4096x4096 window of the L=32768 hot-start lattice (seed 11), T=2.269, {done} sweeps, "
+                      f"{dt:.1f} s on {threads} threads",
+            "single_thread_value": round(single, 5),
+            "single_thread_sample": f"1024x1024 window of the same lattice, {done1} sweeps, {dt1:.1f} s on 1 thread",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 # ---------------------------------------------------------------------------
