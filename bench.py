@@ -229,12 +229,13 @@ def run_graph4096(ising, sweeps=10000, every=10):
     chunks instead of issued one by one from the host."""
     import torch
 
+    # the launch shape of the plain run's default plan for this size
     b = ising.Batch([4096], [7], hot=True)
-    b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=2, tiled_block=256, sweeps_per_graph=100)
+    b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=100)
     b.sweep([2.269], 100, every=every)
     b.close()
     b = ising.Batch([4096], [7], hot=True)
-    b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=2, tiled_block=256, sweeps_per_graph=100)
+    b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=100)
     b.sweep([2.269], 100, every=every)  # capture the chunk graph before timing
     torch.cuda.synchronize()
     e0, e1 = _events()

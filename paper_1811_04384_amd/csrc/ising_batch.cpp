@@ -365,7 +365,7 @@ int create_impl(int32_t n, const int32_t* L, const uint64_t* seed, const int32_t
             if (lattice_bytes(b->geo[i]) <= lim && b->geo[i].L <= 256) p.resident_max_L = std::max(p.resident_max_L, b->geo[i].L);
         p.resident_block = 256;
         p.words_per_thread = 1;
-        p.tiled_block = 128;
+        p.tiled_block = 64;  // fastest measured for small and large batches alike
         p.sweeps_per_graph = 50;
     }
     int rc = apply_plan(b, p);
@@ -622,7 +622,7 @@ int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path
     };
     // 1) tiled shape with everything tiled
     for (int wpt : {1, 2, 4})
-        for (int blk : {128, 256}) {
+        for (int blk : {64, 128, 256}) {
             if (rc != ISING_OK) break;
             ising_batch_plan p = best;
             p.resident_max_L = 0;

@@ -122,10 +122,16 @@ static int create_impl(int32_t L, uint64_t seed, int32_t init, void* dev_words, 
         release(h);
         return fail(ISING_ENOMEM, "ising_create: scratch allocation failed: %s", hipGetErrorString(e));
     }
-    // default plan: two words per thread (fastest measured on gfx950 for
-    // large lattices) unless that leaves the chip short of wavefronts
-    h->wpt = units_per_colour(h->g, 2) >= 64 * 1024 ? 2 : 1;
-    h->block = 256;
+    // default plan (measured on gfx950): from 64 Ki to 1 Mi words per colour
+    // (L from about 1200 to 4600) one word per thread in 64-thread
+    // workgroups is fastest (L = 4096: 1112 against 827 attempts/ns for two
+    // words in 256-thread workgroups); above it the plans are within a few
+    // per cent and two words per thread in 256-thread workgroups is kept;
+    // below it (a handful of workgroups) 256-thread workgroups with one word
+    // per thread
+    const int64_t words = units_per_colour(h->g, 1);
+    h->wpt = words < ((int64_t)1 << 20) ? 1 : 2;
+    h->block = (words >= ((int64_t)1 << 16) && words < ((int64_t)1 << 20)) ? 64 : 256;
     e = launch_init(h->W, h->g, seed, init, h->stream);
     if (e != hipSuccess) {
         release(h);

@@ -244,7 +244,7 @@ int enqueue_quantum(ising_server* s) {
         ISING_HIP(hipMemcpyAsync(s->d_waves, st.waves, sizeof(WaveItem) * n_waves, hipMemcpyHostToDevice, s->stream));
     if (n_res) ISING_HIP(hipMemcpyAsync(s->d_ids, st.ids, sizeof(int32_t) * n_res, hipMemcpyHostToDevice, s->stream));
     if (K > 0) {
-        const int block = 128, rblock = 256;
+        const int block = 64, rblock = 256;
         if (n_res) {
             // the resident lattices (one workgroup each) run on the side
             // stream, overlapping the tiled launches of the other lattices
