@@ -267,7 +267,7 @@ constexpr int64_t kStripBufEntries = int64_t(1) << 22;
 constexpr size_t kStripChainLdsMax = 16 * 1024;
 
 static int strip_phase(ising_lattice* h, const StripArgs& a) {
-    if (strip_chain_lds_bytes(a) > kStripChainLdsMax) {
+    if (strip_chain_lds_bytes(a) > kStripChainLdsMax || strip_apply_lds_bytes(a, 1) > kStripLdsBytes) {
         ISING_HIP(launch_strip_phase(h->W, a, h->stream));
         return ISING_OK;
     }

@@ -49,10 +49,12 @@ hipError_t launch_strip_phase(uint64_t* W, const StripArgs& a, hipStream_t s);
 // The same phase split in chunks of picks: launch_strip_draws computes the
 // words and acceptance codes of picks [k0, k0 + n_k) of every strip into
 // pos / codes (n_k * strips entries, pick-major), launch_strip_apply applies
-// them in order, the strip's columns held in LDS.  Usable when
-// strip_chain_lds_bytes(a) <= kStripLdsBytes.
+// them in order (a window of picks per step, committing the prefix without
+// conflicts), the strips' columns held in LDS.  Usable when one strip fits:
+// strip_apply_lds_bytes(a, 1) <= kStripLdsBytes.
 constexpr size_t kStripLdsBytes = 64 * 1024;
 size_t strip_chain_lds_bytes(const StripArgs& a);
+size_t strip_apply_lds_bytes(const StripArgs& a, int chains);
 hipError_t launch_strip_draws(const StripArgs& a, uint32_t k0, uint32_t n_k, uint32_t* pos, uint64_t* codes,
                               hipStream_t s);
 hipError_t launch_strip_apply(uint64_t* W, const StripArgs& a, uint32_t n_k, const uint32_t* pos,

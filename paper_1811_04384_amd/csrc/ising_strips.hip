@@ -101,11 +101,31 @@ __global__ void __launch_bounds__(256) k_strip_draws(StripArgs a, uint32_t k0, u
     codes_out[i] = assemble_codes(codes);
 }
 
-// One lane per strip; lanes >= chains of a workgroup idle.  LDS column cc of
-// a chain: 0 = the frozen column left of the phase columns, 1..width = the
-// phase columns, width + 1 = the frozen column right of them; N words each.
-// After the chains' columns the LDS holds the live-slot mask of every word
-// row.
+// Apply the drawn picks of a phase.  A workgroup (one wavefront) holds
+// `chains` strips (1, 2 or 4) in LDS and gives each G = 64 / chains lanes.
+// A strip's picks are applied in windows of G picks in pick order: first the
+// picks deferred by the previous step, then the next fresh ones.  A pick of
+// the window conflicts with an earlier pick of the window iff the earlier
+// pick's word is its own word or one it reads (left, right, up, down, the
+// wrap-row patch word); this relation is symmetric (each of these neighbour
+// relations has its mirror).  Every pick without such a conflict is applied
+// now, the others are deferred, in order: a pick applied now commutes with
+// every earlier deferred one (neither reads the other's word), and the
+// picks applied together read no word another of them writes, while every
+// lane of a step loads before any lane stores, so the state is exactly that
+// of applying the picks one by one.  The first pick of a window never
+// conflicts, so every step applies at least one.  Conflicts are found
+// through a claim per word: each lane takes the minimum of its index and the
+// claim of its word, then a lane conflicts iff a word it reads carries a
+// smaller index.
+//
+// LDS per strip q: words [q][cc][I] (cc = 0: the frozen column left of the
+// phase columns, 1..width: the phase columns, width + 1: the frozen column
+// right of them), claims of the same words, the pick data of the current
+// block of kStripBlock picks and the deferred picks; then the live-slot mask
+// of every word row.
+constexpr int kStripBlock = 128;
+
 __global__ void __launch_bounds__(64) k_strip_apply(uint64_t* __restrict__ W, StripArgs a, int chains,
                                                     uint32_t n_k, const uint32_t* __restrict__ pos,
                                                     const uint64_t* __restrict__ codes) {
@@ -114,6 +134,14 @@ __global__ void __launch_bounds__(64) k_strip_apply(uint64_t* __restrict__ W, St
     const int p0 = (int)blockIdx.x * chains;
     const int n_chains = min(chains, a.strips - p0);
     const int L = a.L, N = a.N, width = a.width, cols = width + 2;
+    const int chain_words = cols * N;
+    uint64_t* __restrict__ words = strip_lds;
+    uint64_t* __restrict__ live_row = words + (size_t)chains * chain_words;
+    uint64_t* __restrict__ blk_codes = live_row + N;
+    uint32_t* __restrict__ claims = reinterpret_cast<uint32_t*>(blk_codes + (size_t)chains * kStripBlock);
+    uint32_t* __restrict__ blk_pos = claims + (size_t)chains * chain_words;
+    uint32_t* __restrict__ deferred = blk_pos + (size_t)chains * kStripBlock;  // 64 entries, G per strip
+
     // cooperative fill: entry e = (row I, chain q, LDS column cc) with
     // (q, cc) fastest, so neighbouring threads read neighbouring columns
     const int per_row = n_chains * cols;
@@ -142,46 +170,124 @@ __global__ void __launch_bounds__(64) k_strip_apply(uint64_t* __restrict__ W, St
             if (e < n_fill) {
                 int q, cc, I;
                 fill_col(e, q, cc, I);
-                strip_lds[((size_t)q * cols + cc) * N + I] = v[u];
+                words[(size_t)q * chain_words + (size_t)cc * N + I] = v[u];
             }
         }
     }
-    uint64_t* __restrict__ live_row = strip_lds + (size_t)chains * (size_t)cols * (size_t)N;
     for (int I = lane; I < N; I += 64) live_row[I] = live_mask(I, L, N);
-    __syncthreads();
-    if (lane < n_chains) {
-        const int p = p0 + lane;
-        uint64_t* __restrict__ my = strip_lds + (size_t)lane * (size_t)cols * (size_t)N;
-        const size_t stride = (size_t)a.strips;
-        auto apply = [&](uint32_t pk, uint64_t cd) {
-            const int I = (int)(pk >> kStripColBits);
-            const int cc = (int)(pk & ((1u << kStripColBits) - 1u)) + 1;
-            uint64_t* __restrict__ col = my + cc * N;
-            auto ld = [&](int i, int) { return col[i]; };
-            const uint64_t w = col[I];
-            const uint64_t lf = col[I - N];
-            const uint64_t rt = col[I + N];
-            const uint64_t up = up_word(ld, I, 0, N, a.istar, a.sh_star);
-            const uint64_t dn = down_word(ld, I, 0, N, a.istar, a.sh_star);
-            col[I] = w ^ flip_mask(w, up, dn, lf, rt, cd, live_row[I]);
-        };
-        // the pick data of the next four picks is in flight while one is applied
-        auto at = [&](uint32_t kk) { return (size_t)min(kk, n_k - 1) * stride + (size_t)p; };
-        uint32_t q0 = pos[at(0)], q1 = pos[at(1)], q2 = pos[at(2)], q3 = pos[at(3)];
-        uint64_t d0 = codes[at(0)], d1 = codes[at(1)], d2 = codes[at(2)], d3 = codes[at(3)];
-        uint32_t kk = 0;
-        for (; kk + 4 <= n_k; kk += 4) {
-            uint32_t q;
-            uint64_t e;
-            q = pos[at(kk + 4)], e = codes[at(kk + 4)], apply(q0, d0), q0 = q, d0 = e;
-            q = pos[at(kk + 5)], e = codes[at(kk + 5)], apply(q1, d1), q1 = q, d1 = e;
-            q = pos[at(kk + 6)], e = codes[at(kk + 6)], apply(q2, d2), q2 = q, d2 = e;
-            q = pos[at(kk + 7)], e = codes[at(kk + 7)], apply(q3, d3), q3 = q, d3 = e;
+    for (int e = lane; e < chains * chain_words; e += 64) claims[e] = 0xFFFFFFFFu;
+
+    // lanes of a strip: group q = lane / G, index i = lane % G
+    const int G = 64 / chains;
+    const int q = lane / G;
+    const int i = lane - q * G;
+    const bool has_chain = q < n_chains;
+    uint64_t* __restrict__ my = words + (size_t)q * chain_words;
+    uint32_t* __restrict__ my_claim = claims + (size_t)q * chain_words;
+    const int istar = a.istar, sh_star = a.sh_star;
+    const size_t stride = (size_t)a.strips;
+
+    // pick data of a block: entry e = (chain qq, pick j) with j fastest;
+    // held in registers while the previous block is applied
+    constexpr int kPer = kStripBlock * 4 / 64;  // entries per lane for up to 4 chains
+    const int n_entries = chains * kStripBlock;
+    uint32_t rq[kPer];
+    uint64_t rd[kPer];
+    auto fetch = [&](uint32_t b0) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = lane + 64 * u;
+            const int qq = e / kStripBlock, j = e - (e / kStripBlock) * kStripBlock;
+            const uint32_t k = min(b0 + (uint32_t)j, n_k - 1);
+            const bool ok = e < n_entries && qq < n_chains;
+            const size_t idx = (size_t)k * stride + (size_t)(p0 + (ok ? qq : 0));
+            rq[u] = ok ? pos[idx] : 0u;
+            rd[u] = ok ? codes[idx] : 0ull;
         }
-        if (kk < n_k) apply(q0, d0);
-        if (kk + 1 < n_k) apply(q1, d1);
-        if (kk + 2 < n_k) apply(q2, d2);
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = lane + 64 * u;
+            if (e < n_entries) {
+                blk_pos[e] = rq[u];
+                blk_codes[e] = rd[u];
+            }
+        }
+    };
+    fetch(0u);
+    __syncthreads();
+
+    for (uint32_t b0 = 0; b0 < n_k; b0 += kStripBlock) {
+        stash();
+        fetch(b0 + kStripBlock);  // in flight while this block is applied
+        __syncthreads();
+        const uint32_t bend = min(b0 + (uint32_t)kStripBlock, n_k);
+        uint32_t kk = b0;     // next fresh pick of this strip (same in all its lanes)
+        uint32_t n_def = 0;   // picks of this strip deferred by the previous step
+        const uint64_t gbits = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (q * G));
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes before this one
+        while (true) {
+            const bool pending = has_chain && (n_def > 0u || kk < bend);
+            if (__ballot(pending) == 0ull) break;  // every strip of the workgroup is through the block
+            uint32_t k;
+            bool act;
+            if ((uint32_t)i < n_def) {
+                k = deferred[q * G + i];
+                act = true;
+            } else {
+                k = kk + ((uint32_t)i - n_def);
+                act = has_chain && k < bend;
+            }
+            int w = 0, lf = 0, rt = 0, up = 0, dn = 0, patch = 0, I = 0;
+            uint64_t cd = 0;
+            if (act) {
+                const uint32_t pk = blk_pos[q * kStripBlock + (int)(k - b0)];
+                cd = blk_codes[q * kStripBlock + (int)(k - b0)];
+                I = (int)(pk >> kStripColBits);
+                const int base = ((int)(pk & ((1u << kStripColBits) - 1u)) + 1) * N;
+                w = base + I;
+                lf = w - N;
+                rt = w + N;
+                up = base + (I > 0 ? I - 1 : N - 1);
+                dn = base + (I < N - 1 ? I + 1 : 0);
+                // the patch word of the wrap rows (row I* for I = 0, row 0
+                // for I = I*); other rows read their own word again
+                patch = I == 0 ? base + istar : (I == istar ? base : w);
+                atomicMin(&my_claim[w], (uint32_t)i);
+            }
+            bool conflict = false;
+            uint64_t vw = 0, vlf = 0, vrt = 0, vup = 0, vdn = 0, vpatch = 0, vlive = 0;
+            if (act) {
+                const uint32_t ui = (uint32_t)i;
+                conflict = my_claim[w] < ui || my_claim[lf] < ui || my_claim[rt] < ui || my_claim[up] < ui ||
+                           my_claim[dn] < ui || my_claim[patch] < ui;
+                vw = my[w];
+                vlf = my[lf];
+                vrt = my[rt];
+                vup = my[up];
+                vdn = my[dn];
+                vpatch = my[patch];
+                vlive = live_row[I];
+            }
+            if (act && !conflict) {
+                uint64_t vu = vup, vd = vdn;
+                if (I == 0) vu = (vu >> 3) | (((vpatch >> sh_star) & 1ull) << 60);
+                if (I == N - 1) vd = (vd << 3) & kLow63;
+                if (I == istar) vd = (vd & ~(1ull << sh_star)) | (((vpatch >> 60) & 1ull) << sh_star);
+                my[w] = vw ^ flip_mask(vw, vu, vd, vlf, vrt, cd, vlive);
+            }
+            if (act) my_claim[w] = 0xFFFFFFFFu;
+            // the conflicting picks, in order, head the next window
+            const uint64_t cmask = __ballot(act && conflict) & gbits;
+            const uint64_t amask = __ballot(act) & gbits;
+            if (act && conflict) deferred[q * G + __builtin_popcountll(cmask & below)] = k;
+            kk += (uint32_t)__builtin_popcountll(amask) - n_def;  // fresh picks taken into this window
+            n_def = (uint32_t)__builtin_popcountll(cmask);
+        }
+        __syncthreads();
     }
+
     __syncthreads();
     // cooperative write-back of the phase columns (LDS columns 1..width)
     const int per_row_w = n_chains * width;
@@ -189,16 +295,22 @@ __global__ void __launch_bounds__(64) k_strip_apply(uint64_t* __restrict__ W, St
     for (int e = lane; e < n_back; e += 64) {
         const int I = e / per_row_w;
         const int rem = e - I * per_row_w;
-        const int q = rem / width;
-        const int cc = rem - q * width + 1;
-        const int J = (p0 + q) * a.S + a.off + cc - 1;
-        W[(size_t)I * (size_t)L + (size_t)J] = strip_lds[((size_t)q * cols + cc) * N + I];
+        const int qq = rem / width;
+        const int cc = rem - qq * width + 1;
+        const int J = (p0 + qq) * a.S + a.off + cc - 1;
+        W[(size_t)I * (size_t)L + (size_t)J] = words[(size_t)qq * chain_words + (size_t)cc * N + I];
     }
 }
 
 inline unsigned strip_grid(uint64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
+
+size_t strip_apply_lds_bytes(const StripArgs& a, int chains) {
+    const size_t words = (size_t)chains * (size_t)(a.width + 2) * (size_t)a.N;
+    return words * (sizeof(uint64_t) + sizeof(uint32_t)) + (size_t)a.N * sizeof(uint64_t) +
+           (size_t)chains * kStripBlock * (sizeof(uint64_t) + sizeof(uint32_t)) + 64 * sizeof(uint32_t);
+}
 
 hipError_t launch_strip_phase(uint64_t* W, const StripArgs& a, hipStream_t s) {
     if (a.strips <= 0 || a.picks == 0) return hipSuccess;
@@ -219,12 +331,12 @@ hipError_t launch_strip_draws(const StripArgs& a, uint32_t k0, uint32_t n_k, uin
 hipError_t launch_strip_apply(uint64_t* W, const StripArgs& a, uint32_t n_k, const uint32_t* pos,
                               const uint64_t* codes, hipStream_t s) {
     if (a.strips <= 0 || n_k == 0) return hipSuccess;
-    const size_t per_chain = strip_chain_lds_bytes(a);
-    const size_t live_bytes = (size_t)a.N * sizeof(uint64_t);
-    if (per_chain + live_bytes > kStripLdsBytes) return hipErrorInvalidValue;
-    const int chains = (int)std::min<size_t>(64, (kStripLdsBytes - live_bytes) / per_chain);
-    hipLaunchKernelGGL(k_strip_apply, dim3(strip_grid((uint64_t)a.strips, chains)), dim3(64),
-                       chains * per_chain + live_bytes, s, W, a, chains, n_k, pos, codes);
+    int chains = 2;  // two strips of 32 lanes per wavefront (measured best of 1, 2, 4)
+    while (chains > 1 && strip_apply_lds_bytes(a, chains) > kStripLdsBytes) chains /= 2;
+    const size_t lds = strip_apply_lds_bytes(a, chains);
+    if (lds > kStripLdsBytes) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_strip_apply, dim3(strip_grid((uint64_t)a.strips, chains)), dim3(64), lds, s, W, a, chains,
+                       n_k, pos, codes);
     return hipGetLastError();
 }
 
