@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(256) k_strip_draws(StripArgs a, uint32_t k0, u
 // right of them), claims of the same words, the pick data of the current
 // block of kStripBlock picks and the deferred picks; then the live-slot mask
 // of every word row.
-constexpr int kStripBlock = 128;
+constexpr int kStripBlock = 256;
 
 __global__ void __launch_bounds__(64) k_strip_apply(uint64_t* __restrict__ W, StripArgs a, int chains,
                                                     uint32_t n_k, const uint32_t* __restrict__ pos,
