@@ -224,3 +224,35 @@ def test_l32768_windows_match_oracle():
             assert (got == want).all(), (r, c)
     finally:
         lat.close()
+
+
+def test_largest_lattice_matches_oracle():
+    """The largest lattice the library accepts, L = 2^18 (N = 12484 word
+    rows, 26 GB of words, beyond 4 GiB so the kernels use 64-bit word
+    offsets; I·L + c of the random-number counter still fits 32 bits), in its
+    default launch configuration, 2 sweeps at T = 2.5 from a hot start:
+    windows at the corners (periodic wrap), the last word row and the seam
+    between position 19 and 20, and the interior equal the oracle's exact
+    window evolution; E and M are consistent."""
+    L, seed, T, n = 1 << 18, 5, 2.5, 2
+    N = oracle.word_rows(L)
+    assert N * L < 1 << 32 and 8 * N * L > 1 << 32
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        _log("L=2^18 plan", lat.plan())
+        E, M = lat.sweep_measure(T, n, n)
+        E2, M2 = lat.observables()
+        assert (int(E[0]), int(M[0])) == (E2, M2)
+        assert E2 % 4 == 0 and M2 % 2 == 0 and abs(E2) <= 2 * L * L and abs(M2) <= L * L
+        k = 2 * n + 1
+        h = w = 20
+        spots = [(L - 10, L - 10), (N - 10, 131072), (20 * N - 10, 5), (L - 10, 200000), (100000, L - 4), (4321, 77777)]
+        for (r, c) in spots:
+            r0, c0 = (r - k) % L, (c - k) % L
+            win = oracle.init_window(L, seed, True, r0, c0, h + 2 * k, w + 2 * k)
+            oracle.sweep_window(win, L, seed, 0, n, T, r0, c0)
+            want = win[k:k + h, k:k + w]
+            got = lat.region(r0 + k, c0 + k, h, w)
+            assert (got == want).all(), (r, c)
+    finally:
+        lat.close()
