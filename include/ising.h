@@ -292,6 +292,12 @@ int ising_batch_scan(ising_batch* b, int32_t n_T, const double* T, int64_t therm
 
 /* Spins of lattice i (host array of L[i]^2 bytes); sweep counter of i. */
 int ising_batch_get_spins(ising_batch* b, int32_t i, uint8_t* host_spins);
+/* Spins of the nrows x ncols window of lattice i with top-left site
+   (r0, c0), indices taken modulo L[i], into a host array of nrows*ncols
+   bytes, row major, 1 = up.  1 <= nrows, ncols <= L[i]; EINVAL otherwise or
+   for i out of range.  Synchronises the batch's stream. */
+int ising_batch_get_spins_region(ising_batch* b, int32_t i, int32_t r0, int32_t c0, int32_t nrows, int32_t ncols,
+                                 uint8_t* host);
 int ising_batch_get_sweep_count(ising_batch* b, int32_t i, uint64_t* t);
 
 /* Execution plan.  Lattices with L <= resident_max_L are advanced by one

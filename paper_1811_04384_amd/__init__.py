@@ -278,6 +278,12 @@ def ising_batch_get_spins(h, i, L):
     return out
 
 
+def ising_batch_get_spins_region(h, i, r0, c0, nrows, ncols):
+    out = np.empty((nrows, ncols), dtype=np.uint8)
+    _check(_lib.load().ising_batch_get_spins_region(h, int(i), int(r0), int(c0), int(nrows), int(ncols), _ptr(out)))
+    return out
+
+
 def ising_batch_get_sweep_count(h, i):
     t = ctypes.c_uint64()
     _check(_lib.load().ising_batch_get_sweep_count(h, int(i), ctypes.byref(t)))
@@ -548,6 +554,9 @@ class Batch:
 
     def spins(self, i):
         return ising_batch_get_spins(self.handle, i, self.Ls[i])
+
+    def region(self, i, r0, c0, nrows, ncols):
+        return ising_batch_get_spins_region(self.handle, i, r0, c0, nrows, ncols)
 
     def sweep_count(self, i):
         return ising_batch_get_sweep_count(self.handle, i)

@@ -543,6 +543,28 @@ int ising_batch_scan(ising_batch* b, int32_t n_T, const double* T, int64_t therm
     return ISING_OK;
 }
 
+int ising_batch_get_spins_region(ising_batch* b, int32_t i, int32_t r0, int32_t c0, int32_t nrows, int32_t ncols,
+                                 uint8_t* host) {
+    if (!b || !host) return fail(ISING_EINVAL, "ising_batch_get_spins_region: null argument");
+    if (i < 0 || i >= b->n) return fail(ISING_EINVAL, "ising_batch_get_spins_region: index %d out of range", i);
+    const Geometry& g = b->geo[i];
+    const int32_t L = g.L;
+    if (nrows < 1 || ncols < 1 || nrows > L || ncols > L)
+        return fail(ISING_EINVAL, "ising_batch_get_spins_region: window %dx%d outside 1..L=%d", nrows, ncols, L);
+    const int32_t rr = (int32_t)(((int64_t)r0 % L + L) % L), cc = (int32_t)(((int64_t)c0 % L + L) % L);
+    const size_t bytes = (size_t)nrows * (size_t)ncols;
+    uint8_t* d = nullptr;
+    ISING_HIP(hipMalloc(&d, bytes));
+    hipError_t e = launch_unpack(reinterpret_cast<const uint64_t*>(b->arena + b->offset[i]), g, rr, cc, nrows, ncols,
+                                 d, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipError_t e2 = hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "ising_batch_get_spins_region");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
+    return ISING_OK;
+}
+
 int ising_batch_get_spins(ising_batch* b, int32_t i, uint8_t* host) {
     if (!b || !host) return fail(ISING_EINVAL, "ising_batch_get_spins: null argument");
     if (i < 0 || i >= b->n) return fail(ISING_EINVAL, "ising_batch_get_spins: index %d out of range", i);

@@ -138,3 +138,39 @@ def test_autotune_picks_a_plan_and_keeps_state(tmp_path):
         b2.close()
     finally:
         b.close()
+
+
+def test_lattice_beyond_4gib_in_a_batch():
+    """A batch holding a lattice larger than 4 GiB (L = 110000, N = 5240,
+    4.6 GB, so the tiled kernel takes 64-bit word offsets) beside a small one,
+    tiled, 2 sweeps with a sample: windows of the large lattice at its
+    corners and seams (read with ising_batch_get_spins_region) and all of the
+    small one equal the oracle; the window reader checks its arguments."""
+    Ls, seeds, Ts, n = [110000, 130], [3, 4], [2.5, 2.0], 2
+    N = oracle.word_rows(Ls[0])
+    assert 8 * N * Ls[0] > 1 << 32
+    print("batch with L=110000", flush=True)
+    b = ising.Batch(Ls, seeds, hot=True)
+    try:
+        b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=2)
+        b.sweep(Ts, n, every=n)
+        res = b.results()
+        L, seed, T = Ls[0], seeds[0], Ts[0]
+        k, h, w = 2 * n + 1, 16, 16
+        for (r, c) in [(L - 8, L - 8), (N - 8, 55000), (20 * N - 8, 3), (12345, 67890)]:
+            r0, c0 = (r - k) % L, (c - k) % L
+            win = oracle.init_window(L, seed, True, r0, c0, h + 2 * k, w + 2 * k)
+            oracle.sweep_window(win, L, seed, 0, n, T, r0, c0)
+            assert (b.region(0, r0 + k, c0 + k, h, w) == win[k:k + h, k:k + w]).all(), (r, c)
+        s = oracle.init(Ls[1], seeds[1], True)
+        oracle.sweep(s, seeds[1], 0, n, Ts[1])
+        assert (b.spins(1) == s).all()
+        assert (b.region(1, 0, 0, 130, 130) == s).all()
+        assert (b.region(1, -3, 127, 5, 7) == np.roll(np.roll(s, 3, 0), -127, 1)[:5, :7]).all()
+        assert (int(res["E"][1]), int(res["M"][1])) == oracle.observables(s)
+        assert int(res["E"][0]) % 4 == 0 and int(res["M"][0]) % 2 == 0
+        for bad in [(2, 0, 0, 1, 1), (0, 0, 0, 0, 4), (1, 0, 0, 131, 1)]:
+            with pytest.raises(ising.IsingError):
+                b.region(*bad)
+    finally:
+        b.close()
