@@ -35,9 +35,10 @@ if ROOT not in sys.path:
 METRIC = "spin-flip attempts/ns (L=32768 single; batched mixed-L) + p50/p99 latency"
 UNIT = "attempts/ns"
 
-# Integer-ALU roofline: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
-# single-slot 32-bit lane operations per second, the rate that gives the
-# published 157.3 TFLOP/s FP32 vector peak when a lane op is an FMA.
+# Integer-ALU roofline: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz single-slot
+# 32-bit lane operations per second, the rate that gives the published
+# 157.3 TFLOP/s FP32 vector peak when a lane op is an FMA, and the rate at
+# which simple 32-bit vector operations issue (bench.py --valu-rates).
 ALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # Algorithmic integer lane-op slots per spin-flip attempt: a quarter of one
 # Philox4x32-10 block (10 rounds x (2 wide 32x32->64 products at 2 slots
@@ -512,8 +513,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the lattice kernels run on a single MI355X and this build has no "
-              "multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the lattice kernels run on a single MI355X and there is no "
+              "multi-GPU path (a single lattice would shard by word-column strips with one boundary-column "
+              "exchange per half-sweep; batches and served requests by whole lattices).", file=sys.stderr)
         sys.exit(2)
 
     if args.valu_rates:  # a child process of its own, started before this one touches the GPU
