@@ -85,9 +85,12 @@ def run_main(ising, steps, warmup, sweeps):
     for _ in range(warmup):
         one_step(False)
     torch.cuda.synchronize()
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        results = one_step(True)
+        ts = time.perf_counter()
+        results = one_step(True)  # ends synchronised (observables)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     lat.close()
@@ -99,6 +102,7 @@ def run_main(ising, steps, warmup, sweeps):
         "ms_per_step": ms_per_step,
         "value": attempts / (ms_per_step * 1e6),
         "avg_halfsweep_ms": avg_launch_ms,
+        "step_ms": step_ms,
         "plan": {"words_per_thread": wpt, "block": block},
         "final": results,
     }
@@ -489,7 +493,7 @@ def run_serving(ising, rate=25.0, duration=10.0, quantum=100, seed=2026, slots=1
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sweeps", type=int, default=SWEEPS_MAIN, help="sweeps per temperature (headline: 2000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -601,6 +605,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(main_res["ms_per_step"], 2),
+        "step_ms": [round(x, 2) for x in main_res["step_ms"]],
+        "value_median_step": round(len(TEMPS_MAIN) * args.sweeps * L_MAIN ** 2
+                                   / (sorted(main_res["step_ms"])[len(main_res["step_ms"]) // 2] * 1e6), 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
