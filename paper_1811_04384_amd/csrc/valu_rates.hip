@@ -165,6 +165,7 @@ VR_KERNEL32(k_cmp_add, OP_CMP)
                  a12 = a0 + 12, a13 = a0 + 13, a14 = a0 + 14, a15 = a0 + 15;                         \
         const uint32_t b = tid * 0x9E3779B9u;                                                        \
         const uint32_t vk = k ^ (tid & 1u); /* the multiplier, in a vector register */               \
+        const uint64_t vmask = mask ^ (tid & 1u); /* a 64-bit addend, in vector registers */         \
         VR_SGPRS                                                                                     \
         for (int it = 0; it < kIters; ++it) { VR_16(ASM_OP) }                                        \
         const uint64_t r = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7 ^ a8 ^ a9 ^ a10 ^ a11 ^ a12 ^ a13 ^ a14 ^ a15 ^ \
@@ -176,9 +177,81 @@ VR_KERNEL32(k_cmp_add, OP_CMP)
 #define OP_MAD64_V(a) asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(a), "=s"(s_##a) : "v"(b), "v"(vk));
 #define OP_SHL64(a) asm volatile("v_lshlrev_b64 %0, 3, %0" : "+v"(a));
 
+#define OP_LSA_S(a) asm volatile("v_lshl_add_u64 %0, %0, 0, %1" : "+v"(a) : "s"(mask));
+#define OP_LSA_V(a) asm volatile("v_lshl_add_u64 %0, %0, 0, %1" : "+v"(a) : "v"(vmask));
+
 VR_KERNEL64(k_mad_u64, OP_MAD64)
 VR_KERNEL64(k_mad_u64_v, OP_MAD64_V)
 VR_KERNEL64(k_lshl_b64, OP_SHL64)
+VR_KERNEL64(k_lsa_s, OP_LSA_S)
+VR_KERNEL64(k_lsa_v, OP_LSA_V)
+
+// The acceptance code of one site appended to an accumulator, both ways the
+// half-sweep can compute it (thresholds in scalar registers, the draw in a
+// vector register): two compares into lane masks, two selects and a
+// shift-or; or two 64-bit adds whose carries are the code bits, with the
+// accumulator as the high word, and two shifts.  One chain step is one site.
+__device__ __forceinline__ uint32_t vr_accept_cmp(uint32_t acc, uint32_t u, uint32_t t4, uint32_t t8) {
+    uint32_t x;
+    uint64_t m4, m8;
+    asm volatile("v_cmp_gt_u32_e64 %[m4], %[t4], %[u]\n\t"
+                 "v_cmp_gt_u32_e64 %[m8], %[t8], %[u]\n\t"
+                 "s_nop 1\n\t"
+                 "v_cndmask_b32_e64 %[x], 0, 1, %[m4]\n\t"
+                 "v_cndmask_b32_e64 %[x], %[x], 2, %[m8]\n\t"
+                 "v_lshl_or_b32 %[acc], %[acc], 3, %[x]"
+                 : [acc] "+v"(acc), [x] "=&v"(x), [m4] "=&s"(m4), [m8] "=&s"(m8)
+                 : [u] "v"(u), [t4] "s"(t4), [t8] "s"(t8));
+    return acc;
+}
+template <int S>
+__device__ __forceinline__ uint32_t vr_shl(uint32_t x) {
+    uint32_t r;
+    asm volatile("v_lshlrev_b32 %0, %1, %2" : "=v"(r) : "i"(S), "v"(x));
+    return r;
+}
+__device__ __forceinline__ uint64_t vr_add64(uint64_t x, uint64_t k) {
+    uint64_t r;
+    asm volatile("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(k));
+    return r;
+}
+__device__ __forceinline__ uint32_t vr_accept_add64(uint32_t acc, uint32_t u, uint64_t k4, uint64_t k48) {
+    const uint64_t p = vr_add64(((uint64_t)vr_shl<2>(acc) << 32) | u, k4);
+    return (uint32_t)(vr_add64(((uint64_t)vr_shl<1>((uint32_t)(p >> 32)) << 32) | (uint32_t)p, k48) >> 32);
+}
+// compares into VCC and adds with carry-in: acc = ((4 acc + b4) << 1) + b8,
+// with the two wait states a VALU read of a VALU-written VCC needs
+__device__ __forceinline__ uint32_t vr_accept_vcc(uint32_t acc, uint32_t u, uint32_t t4, uint32_t t8) {
+    asm volatile("v_lshlrev_b32_e32 %[acc], 1, %[acc]\n\t"
+                 "v_cmp_gt_u32_e32 vcc, %[t4], %[u]\n\t"
+                 "s_nop 1\n\t"
+                 "v_addc_co_u32_e32 %[acc], vcc, %[acc], %[acc], vcc\n\t"
+                 "v_cmp_gt_u32_e32 vcc, %[t8], %[u]\n\t"
+                 "s_nop 1\n\t"
+                 "v_addc_co_u32_e32 %[acc], vcc, %[acc], %[acc], vcc"
+                 : [acc] "+v"(acc)
+                 : [u] "v"(u), [t4] "s"(t4), [t8] "s"(t8)
+                 : "vcc");
+    return acc;
+}
+#define OP_ACC_CMP(a) a = vr_accept_cmp(a, b, k, k >> 1);
+#define OP_ACC_VCC(a) a = vr_accept_vcc(a, b, k, k >> 1);
+#define OP_CMP32(a)                                                                     \
+    {                                                                                   \
+        asm volatile("v_cmp_gt_u32_e32 vcc, %0, %1" : : "s"(k), "v"(a) : "vcc");       \
+        asm volatile("v_add_u32_e32 %0, 1, %0" : "+v"(a));                              \
+    }
+#define OP_CNDMASK32(a) asm volatile("v_cndmask_b32_e32 %0, %0, %1, vcc" : "+v"(a) : "v"(b));
+#define OP_CNDMASK_VCC64(a) asm volatile("v_cndmask_b32_e64 %0, %0, %1, vcc" : "+v"(a) : "v"(b));
+#define OP_MIX_CNDMASK32(a) OP_CNDMASK32(a) OP_ADD_V(a)
+#define OP_ACC_ADD64(a) a = vr_accept_add64(a, b, mask, mask >> 1);
+VR_KERNEL32(k_acc_cmp, OP_ACC_CMP)
+VR_KERNEL32(k_acc_add64, OP_ACC_ADD64)
+VR_KERNEL32(k_acc_vcc, OP_ACC_VCC)
+VR_KERNEL32(k_cmp32_add, OP_CMP32)
+VR_KERNEL32(k_cndmask32, OP_CNDMASK32)
+VR_KERNEL32(k_cndmask_vcc64, OP_CNDMASK_VCC64)
+VR_KERNEL32(k_mix_cndmask32_add, OP_MIX_CNDMASK32)
 
 typedef void (*Kernel)(uint32_t*, uint32_t, uint64_t);
 
@@ -186,6 +259,7 @@ struct Case {
     const char* name;
     Kernel fn;
     int instr_per_op;  // vector instructions per chain step
+    const char* per = "instruction";  // what one reported figure covers
 };
 
 }  // namespace
@@ -234,9 +308,18 @@ int main() {
         {"v_mad_u64_u32 (s)", k_mad_u64, 1},
         {"v_mad_u64_u32 (v)", k_mad_u64_v, 1},
         {"v_lshlrev_b64 (c)", k_lshl_b64, 1},
+        {"v_lshl_add_u64 (s)", k_lsa_s, 1},
+        {"v_lshl_add_u64 (v)", k_lsa_v, 1},
+        {"v_cmp_gt_u32_e32 (s, into VCC) + v_add_u32 (c)", k_cmp32_add, 2},
+        {"v_cndmask_b32_e32 (VCC)", k_cndmask32, 1},
+        {"v_cndmask_b32_e64 (VCC)", k_cndmask_vcc64, 1},
+        {"v_cndmask_b32_e32 (VCC) / v_add_u32 (v) alternating", k_mix_cndmask32_add, 2},
+        {"acceptance code per site: compares, selects, shift-or", k_acc_cmp, 1, "site"},
+        {"acceptance code per site: compares into VCC, adds with carry", k_acc_vcc, 1, "site"},
+        {"acceptance code per site: two 64-bit adds, two shifts", k_acc_add64, 1, "site"},
     };
     const int n_cases = (int)(sizeof cases / sizeof cases[0]);
-    double cyc[32];
+    double cyc[64];
     std::printf("device %s (%s), %d CUs, nominal clock %.0f MHz, %d wavefronts per SIMD\n", prop.name,
                 prop.gcnArchName, cus, clock_hz / 1e6, kWavesPerSimd);
     for (int c = 0; c < n_cases; ++c) {
@@ -255,7 +338,7 @@ int main() {
         ms /= reps;
         const double instr_per_simd = (double)kWavesPerSimd * kIters * 16 * cases[c].instr_per_op;
         cyc[c] = ms * 1e-3 * clock_hz / instr_per_simd;
-        std::printf("%-48s %8.3f ms  %5.2f cycles per wave64 instruction\n", cases[c].name, ms, cyc[c]);
+        std::printf("%-56s %8.3f ms  %5.2f cycles per wave64 %s\n", cases[c].name, ms, cyc[c], cases[c].per);
     }
     std::printf("{\"probe\": \"valu_rates\", \"arch\": \"%s\", \"cus\": %d, \"clock_mhz\": %.0f, \"cycles\": {", prop.gcnArchName,
                 cus, clock_hz / 1e6);
