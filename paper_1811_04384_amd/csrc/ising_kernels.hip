@@ -115,10 +115,26 @@ __device__ __forceinline__ void energy_magnetisation(uint64_t anti, uint64_t ups
 // sweep into its sample: series entry, moment sums, last E and M.
 __device__ __forceinline__ void finalize_lattice(const LatticeDesc& d, LatticeState& st,
                                                  const Partial* __restrict__ partials) {
+    // Every lane sums every 64th partial, eight loads in flight at a time: a
+    // lattice has one partial per wavefront (6272 at L = 4096), and one load
+    // waited for at a time made this wavefront, and with it the launch it
+    // rides in, wait out ~100 memory latencies.  Indexes past the end are
+    // clamped to the last partial (so every load is unconditional and in
+    // bounds) and their values dropped.
+    constexpr int kInFlight = 8;
+    const Partial* __restrict__ part = partials + d.part_begin;
+    const int n = d.part_count;
     unsigned long long anti = 0, ups = 0;
-    for (int i = (int)lane_id(); i < d.part_count; i += 64) {
-        anti += partials[d.part_begin + i].anti;
-        ups += partials[d.part_begin + i].ups;
+    for (int i0 = (int)lane_id(); i0 < n; i0 += 64 * kInFlight) {
+        Partial v[kInFlight];
+#pragma unroll
+        for (int k = 0; k < kInFlight; ++k) v[k] = part[min(i0 + 64 * k, n - 1)];
+#pragma unroll
+        for (int k = 0; k < kInFlight; ++k) {
+            const bool in = i0 + 64 * k < n;
+            anti += in ? v[k].anti : 0u;
+            ups += in ? v[k].ups : 0u;
+        }
     }
     anti = wave_sum_u64(anti);
     ups = wave_sum_u64(ups);
