@@ -297,7 +297,9 @@ def run_scan64(ising, therm=2000, meas=2000):
 
     Ts = [1.5 + 2.0 * i / 7 for i in range(8)]
     b = ising.Batch([64] * 8, [1234] * 8, hot=False)
-    b.set_plan(resident_max_L=64, resident_block=64, words_per_thread=1, tiled_block=256, sweeps_per_graph=500)
+    # 128 threads: one per word of a colour (N = 4 word rows x 64 columns / 2),
+    # so that each half-sweep is one pass over two wavefronts
+    b.set_plan(resident_max_L=64, resident_block=128, words_per_thread=1, tiled_block=256, sweeps_per_graph=500)
     torch.cuda.synchronize()
     e0, e1 = _events()
     e0.record()
