@@ -293,16 +293,54 @@ __device__ __forceinline__ void measure_word(uint64_t w, uint64_t up, uint64_t d
     ups += __popcll(w & live) + __popcll(lf & live);
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// Sums over the 64 lanes of a wavefront, returned to every lane; every lane
+// must be active.  Data-parallel-primitive moves inside the vector unit, no
+// LDS: within each row of 16 lanes, add the neighbour (quad_perm [1,0,3,2]),
+// the neighbouring pair ([2,3,0,1]), the mirror within 8 and the mirror
+// within 16, so that every lane holds its row's sum; then rows 1 and 3 add
+// lane 15 of the row before (row_bcast:15), rows 2 and 3 add lane 31
+// (row_bcast:31), and lane 63 holds the total.  Lanes of a row that a step
+// leaves out add 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+    return ((unsigned long long)dpp_u32<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) | dpp_u32<CTRL, ROWS>((uint32_t)v);
+}
+
+template <class T, class Move>
+__device__ __forceinline__ T wave_sum_steps(T v, Move) {
+    v += Move::template step<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += Move::template step<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += Move::template step<0x141, 0xF>(v);  // row_half_mirror
+    v += Move::template step<0x140, 0xF>(v);  // row_mirror
+    v += Move::template step<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+    v += Move::template step<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
     return v;
 }
 
+struct DppMove32 {
+    template <int C, int R>
+    __device__ static uint32_t step(uint32_t v) { return dpp_u32<C, R>(v); }
+};
+struct DppMove64 {
+    template <int C, int R>
+    __device__ static unsigned long long step(unsigned long long v) { return dpp_u64<C, R>(v); }
+};
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    v = wave_sum_steps(v, DppMove32{});
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = wave_sum_steps(v, DppMove64{});
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 // Update the WPT same-colour words (I, J0 + 2k), k < WPT, of one row segment.
