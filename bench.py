@@ -292,12 +292,12 @@ def run_batched(ising, sweeps=5000, every=10):
             "plain_same_mix": plain, "batched_over_plain": round(value / plain["value"], 2)}
 
 
-def run_batched_as_plain(ising, Ls, Ts, seeds, sweeps=500, every=10):
+def run_batched_as_plain(ising, Ls, Ts, seeds, sweeps=2000, every=10):
     """The batched mix run the plain way, one lattice per launch and one
     lattice after another, on a sample: lattices 0..3 of the mix (one of each
-    size, with their seeds and temperatures), 500 sweeps each with E/M every
-    10.  The mix holds the four sizes in equal numbers, so the sample's rate
-    is the mix's rate."""
+    size, with their seeds and temperatures), 2000 sweeps each with E/M every
+    10 (about 60 ms).  The mix holds the four sizes in equal numbers, so the
+    sample's rate is the mix's rate."""
     import torch
 
     lats = [ising.Lattice(Ls[i], seeds[i], hot=True) for i in range(4)]
