@@ -314,6 +314,12 @@ typedef struct {
     int32_t sweeps_per_graph; /* >= 1                                        */
 } ising_batch_plan;
 
+/* Validate a plan without a batch (host only, no GPU needed): ISING_OK or
+   EINVAL with the reason.  resident_max_L must be in [0, 4096]: one
+   workgroup per lattice is only sensible for lattices that fit, or nearly
+   fit, in one workgroup's LDS.  ising_batch_set_plan applies the same
+   checks. */
+int ising_batch_check_plan(const ising_batch_plan* plan);
 int ising_batch_set_plan(ising_batch* b, const ising_batch_plan* plan);
 int ising_batch_get_plan(ising_batch* b, ising_batch_plan* plan);
 

@@ -51,6 +51,51 @@ def _stream(stream):
     return ctypes.c_void_p(int(stream))
 
 
+class _Ordering:
+    """Orders torch's current stream and a handle's own stream around a call
+    that enqueues library work: before it, the library's stream waits for
+    what torch has enqueued (e.g. the zeroing of an accumulator); after it,
+    torch's current stream waits for the library's work, and the output
+    tensors are marked as used on the library's stream, so that neither a
+    read through torch nor the caching allocator's reuse can overtake the
+    kernels that write them.  Nothing to do when the handle uses torch's
+    current stream."""
+
+    def __init__(self, stream):
+        self.stream = stream
+
+    def _lib(self):
+        import torch
+
+        if self.stream is None:
+            return None
+        if isinstance(self.stream, torch.cuda.Stream):
+            s = self.stream
+        elif hasattr(self.stream, "cuda_stream"):
+            s = torch.cuda.ExternalStream(self.stream.cuda_stream)
+        else:
+            s = torch.cuda.ExternalStream(int(self.stream))
+        return None if s.cuda_stream == torch.cuda.current_stream().cuda_stream else s
+
+    def before(self):
+        import torch
+
+        s = self._lib()
+        if s is not None:
+            s.wait_stream(torch.cuda.current_stream())
+
+    def after(self, *tensors):
+        import torch
+
+        s = self._lib()
+        if s is None:
+            return
+        for t in tensors:
+            if t is not None:
+                t.record_stream(s)
+        torch.cuda.current_stream().wait_stream(s)
+
+
 def _ptr(x):
     """Device or host address of a torch tensor / numpy array / int / None."""
     if x is None:
@@ -290,6 +335,11 @@ def ising_batch_get_sweep_count(h, i):
     return int(t.value)
 
 
+def ising_batch_check_plan(plan):
+    p = plan if isinstance(plan, BatchPlan) else BatchPlan(**plan)
+    _check(_lib.load().ising_batch_check_plan(ctypes.byref(p)))
+
+
 def ising_batch_set_plan(h, plan):
     p = plan if isinstance(plan, BatchPlan) else BatchPlan(**plan)
     _check(_lib.load().ising_batch_set_plan(h, ctypes.byref(p)))
@@ -418,8 +468,11 @@ class Lattice:
         if nbytes == 0:
             raise IsingError(ISING_EINVAL, f"invalid lattice size L={L}")
         self.stream = stream
+        self._order = _Ordering(stream)
         self.words = torch.empty(nbytes // 8, dtype=torch.int64, device=device)
+        self._order.before()  # the block may still be in use by work on torch's stream
         self.handle = ising_create_in(self.L, self.seed, ISING_HOT if hot else ISING_COLD, self.words, nbytes, stream)
+        self._order.after(self.words)
 
     def reset(self, seed=None, hot=True):
         if seed is not None:
@@ -438,7 +491,9 @@ class Lattice:
         k = int(n) // int(every)
         E = torch.empty(max(k, 1), dtype=torch.int64, device=self.words.device)
         M = torch.empty(max(k, 1), dtype=torch.int64, device=self.words.device)
+        self._order.before()
         ising_sweep_measure(self.handle, T, n, every, E, M)
+        self._order.after(E, M)
         return E[:k], M[:k]
 
     def sweep_moments(self, T, n, every, acc=None):
@@ -447,7 +502,9 @@ class Lattice:
 
         if acc is None:
             acc = torch.zeros(10, dtype=torch.int64, device=self.words.device)
+        self._order.before()
         ising_sweep_moments(self.handle, T, n, every, acc)
+        self._order.after(acc)
         return acc
 
     def scan(self, T, therm, meas, every=1):
@@ -462,7 +519,9 @@ class Lattice:
             k = int(n) // int(every)
             E = torch.empty(max(k, 1), dtype=torch.int64, device=self.words.device)
             M = torch.empty(max(k, 1), dtype=torch.int64, device=self.words.device)
+            self._order.before()
             ising_random_iterations(self.handle, T, strip_cols, n, every, E, M, acc)
+            self._order.after(E, M, acc)
             return E[:k], M[:k]
         ising_random_iterations(self.handle, T, strip_cols, n, 0)
         return None
@@ -518,6 +577,7 @@ class Batch:
         self.Ls = [int(x) for x in Ls]
         hots = [hot] * len(self.Ls) if isinstance(hot, bool) else list(hot)
         inits = [ISING_HOT if h else ISING_COLD for h in hots]
+        self._order = _Ordering(stream)
         self.handle = ising_batch_create(self.Ls, seeds, inits, stream)
 
     def __len__(self):
@@ -531,7 +591,9 @@ class Batch:
             k = int(n) // int(every)
             E = torch.empty(max(1, len(self.Ls) * k), dtype=torch.int64, device="cuda")
             M = torch.empty_like(E)
+            self._order.before()
             ising_batch_sweep(self.handle, T, n, every, E, M)
+            self._order.after(E, M)
             return E[: len(self.Ls) * k].view(len(self.Ls), k), M[: len(self.Ls) * k].view(len(self.Ls), k)
         ising_batch_sweep(self.handle, T, n, every)
         return None
@@ -588,6 +650,7 @@ class Replicas:
 
     def __init__(self, L, seed, hot=True, stream=None):
         self.L = int(L)
+        self._order = _Ordering(stream)
         self.handle = ising_replicas_create(self.L, seed, ISING_HOT if hot else ISING_COLD, stream)
 
     def sweep(self, T, n):
@@ -601,7 +664,9 @@ class Replicas:
         k = int(n) // int(every)
         E = torch.empty(max(k, 1) * REPLICAS, dtype=torch.int64, device="cuda")
         M = torch.empty_like(E)
+        self._order.before()
         ising_replicas_sweep_measure(self.handle, T, n, every, E, M)
+        self._order.after(E, M)
         return E[: k * REPLICAS].view(k, REPLICAS), M[: k * REPLICAS].view(k, REPLICAS)
 
     def sweep_moments(self, T, n, every, acc=None):
@@ -610,7 +675,9 @@ class Replicas:
 
         if acc is None:
             acc = torch.zeros(REPLICAS * 10, dtype=torch.int64, device="cuda")
+        self._order.before()
         ising_replicas_sweep_moments(self.handle, T, n, every, acc)
+        self._order.after(acc)
         return acc
 
     def moments(self, acc):

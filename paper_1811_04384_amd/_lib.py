@@ -83,6 +83,7 @@ SIGNATURES = {
     "ising_batch_get_spins": (c_int, [c_vp, c_i32, c_vp]),
     "ising_batch_get_spins_region": (c_int, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp]),
     "ising_batch_get_sweep_count": (c_int, [c_vp, c_i32, P(c_u64)]),
+    "ising_batch_check_plan": (c_int, [P(BatchPlan)]),
     "ising_batch_set_plan": (c_int, [c_vp, P(BatchPlan)]),
     "ising_batch_get_plan": (c_int, [c_vp, P(BatchPlan)]),
     "ising_batch_autotune": (c_int, [c_vp, P(c_dbl), c_char_p, P(BatchPlan)]),

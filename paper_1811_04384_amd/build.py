@@ -12,7 +12,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libising.so")
-VALU_RATES = os.path.join(HERE, "valu_rates")  # microbenchmark program
 ARCH = "gfx950"
 
 SOURCES = [s for s in ["ising_kernels.hip", "ising_strips.hip", "ising_replicas.hip", "ising_lattice.cpp",
@@ -67,24 +66,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
-    build_valu_rates(verbose)
     return LIB
-
-
-def build_valu_rates(verbose: bool = False) -> str:
-    """The instruction-rate microbenchmark (csrc/valu_rates.hip), a program
-    of its own: it measures the issue cost of the vector instructions the
-    half-sweep kernels use and is run by ``bench.py --valu-rates``."""
-    tmp = VALU_RATES + ".tmp"
-    cmd = ([HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}"] + DEVICE_ONLY +
-           [os.path.join(CSRC, "valu_rates.hip"), "-o", tmp])
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for valu_rates.hip:\n{r.stdout}{r.stderr}")
-    os.replace(tmp, VALU_RATES)
-    return VALU_RATES
 
 
 if __name__ == "__main__":

@@ -61,6 +61,8 @@ struct ising_batch {
     int32_t n_glb = 0;
     int32_t n_tiled = 0;
     bool off32 = true;  // every tiled lattice < 4 GiB
+    uint8_t* d_stage = nullptr;  // spin output staging, spin_stage_bytes of the largest L
+    size_t stage_bytes = 0;
     std::map<std::pair<int32_t, int32_t>, hipGraphExec_t> graphs;  // (sweeps, every) -> executable
 };
 
@@ -87,6 +89,7 @@ void release(ising_batch* b) {
     free_dev(b->d_partials);
     free_dev(b->d_ids_lds);
     free_dev(b->d_ids_glb);
+    free_dev(b->d_stage);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
     if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     if (b->join_ev) (void)hipEventDestroy(b->join_ev);
@@ -98,8 +101,15 @@ void release(ising_batch* b) {
 
 size_t lattice_bytes(const Geometry& g) { return (size_t)g.N * (size_t)g.L * sizeof(uint64_t); }
 
+// Largest L a plan may mark resident (one workgroup per lattice).  The
+// lattices of the largest such size (N = 196, 6.4 MB) no longer fit in LDS
+// and are already far slower with one workgroup each than tiled; larger ones
+// would put a multi-gigabyte lattice on a single workgroup.
+constexpr int32_t kResidentMaxL = 4096;
+
 int check_plan(const ising_batch_plan& p) {
-    if (p.resident_max_L < 0) return fail(ISING_EINVAL, "plan: resident_max_L must be >= 0");
+    if (p.resident_max_L < 0 || p.resident_max_L > kResidentMaxL)
+        return fail(ISING_EINVAL, "plan: resident_max_L must be in [0, %d] (got %d)", kResidentMaxL, p.resident_max_L);
     if (!valid_block(p.resident_block, 1024)) return fail(ISING_EINVAL, "plan: resident_block must be a multiple of 64 in [64, 1024]");
     if (p.words_per_thread != 1 && p.words_per_thread != 2 && p.words_per_thread != 4)
         return fail(ISING_EINVAL, "plan: words_per_thread must be 1, 2 or 4");
@@ -339,6 +349,8 @@ int create_impl(int32_t n, const int32_t* L, const uint64_t* seed, const int32_t
         release(b);
         return fail(ISING_ENOMEM, "ising_batch_create: hipMalloc of %zu bytes failed", off);
     }
+    for (int32_t i = 0; i < n; ++i) b->stage_bytes = std::max(b->stage_bytes, spin_stage_bytes(L[i]));
+    if (e == hipSuccess) e = hipMalloc(&b->d_stage, b->stage_bytes);
     if (e == hipSuccess) e = hipMalloc(&b->d_desc, sizeof(LatticeDesc) * n);
     if (e == hipSuccess) e = hipMalloc(&b->d_state, sizeof(LatticeState) * n);
     if (e == hipSuccess) e = hipHostMalloc(&b->h_desc, sizeof(LatticeDesc) * n, hipHostMallocDefault);
@@ -553,33 +565,16 @@ int ising_batch_get_spins_region(ising_batch* b, int32_t i, int32_t r0, int32_t 
     if (nrows < 1 || ncols < 1 || nrows > L || ncols > L)
         return fail(ISING_EINVAL, "ising_batch_get_spins_region: window %dx%d outside 1..L=%d", nrows, ncols, L);
     const int32_t rr = (int32_t)(((int64_t)r0 % L + L) % L), cc = (int32_t)(((int64_t)c0 % L + L) % L);
-    const size_t bytes = (size_t)nrows * (size_t)ncols;
-    uint8_t* d = nullptr;
-    ISING_HIP(hipMalloc(&d, bytes));
-    hipError_t e = launch_unpack(reinterpret_cast<const uint64_t*>(b->arena + b->offset[i]), g, rr, cc, nrows, ncols,
-                                 d, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    hipError_t e2 = hipFree(d);
-    if (e != hipSuccess) return hip_fail(e, "ising_batch_get_spins_region");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
-    return ISING_OK;
+    return read_spin_window(reinterpret_cast<const uint64_t*>(b->arena + b->offset[i]), g, rr, cc, nrows, ncols, host,
+                            b->d_stage, b->stage_bytes, b->stream);
 }
 
 int ising_batch_get_spins(ising_batch* b, int32_t i, uint8_t* host) {
     if (!b || !host) return fail(ISING_EINVAL, "ising_batch_get_spins: null argument");
     if (i < 0 || i >= b->n) return fail(ISING_EINVAL, "ising_batch_get_spins: index %d out of range", i);
     const Geometry& g = b->geo[i];
-    const size_t bytes = (size_t)g.L * (size_t)g.L;
-    uint8_t* d = nullptr;
-    ISING_HIP(hipMalloc(&d, bytes));
-    hipError_t e = launch_unpack(reinterpret_cast<const uint64_t*>(b->arena + b->offset[i]), g, 0, 0, g.L, g.L, d, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    hipError_t e2 = hipFree(d);
-    if (e != hipSuccess) return hip_fail(e, "ising_batch_get_spins");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
-    return ISING_OK;
+    return read_spin_window(reinterpret_cast<const uint64_t*>(b->arena + b->offset[i]), g, 0, 0, g.L, g.L, host,
+                            b->d_stage, b->stage_bytes, b->stream);
 }
 
 int ising_batch_get_sweep_count(ising_batch* b, int32_t i, uint64_t* t) {
@@ -587,6 +582,11 @@ int ising_batch_get_sweep_count(ising_batch* b, int32_t i, uint64_t* t) {
     if (i < 0 || i >= b->n) return fail(ISING_EINVAL, "ising_batch_get_sweep_count: index %d out of range", i);
     *t = b->t_host[i];
     return ISING_OK;
+}
+
+int ising_batch_check_plan(const ising_batch_plan* plan) {
+    if (!plan) return fail(ISING_EINVAL, "ising_batch_check_plan: null plan");
+    return check_plan(*plan);
 }
 
 int ising_batch_set_plan(ising_batch* b, const ising_batch_plan* plan) {
@@ -656,10 +656,13 @@ int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path
             p.sweeps_per_graph = std::min(sweeps, 20);
             rc = consider(p);
         }
-    // 2) which sizes go resident, and the resident workgroup size
+    // 2) which sizes go resident, and the resident workgroup size: only sizes
+    // whose lattice fits one workgroup's LDS are tried
     const ising_batch_plan tiled_best = best;
+    const size_t lds_limit = resident_lds_limit(b->device);
     for (int32_t Lr : distinct)
         for (int rb : {256, 512, 1024}) {
+            if (lattice_bytes(make_geometry(Lr)) > lds_limit) break;
             if (rc != ISING_OK) break;
             ising_batch_plan p = tiled_best;
             p.resident_max_L = Lr;

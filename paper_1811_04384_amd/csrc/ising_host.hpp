@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdarg>
@@ -62,5 +63,21 @@ inline void thresholds_of(double T, uint32_t* t4, uint32_t* t8) {
 }
 
 inline bool valid_block(int b, int max_block) { return b >= 64 && b <= max_block && b % 64 == 0; }
+
+// Spin input/output goes through a byte staging buffer in device memory that
+// a handle allocates once, at creation: the whole L x L lattice when it is
+// small, else 16 MiB, moved in pieces of whole rows.  No call that reads or
+// writes spins allocates or frees device memory.
+constexpr size_t kSpinStageMax = size_t(16) << 20;
+inline size_t spin_stage_bytes(int32_t L) { return std::min((size_t)L * (size_t)L, kSpinStageMax); }
+
+// The nrows x ncols window with top-left site (r0, c0), indices mod L, into
+// host bytes (row major, 1 = up), staged through `stage` (cap bytes >= ncols);
+// synchronises the stream.
+int read_spin_window(const uint64_t* W, const Geometry& g, int32_t r0, int32_t c0, int32_t nrows, int32_t ncols,
+                     uint8_t* host, uint8_t* stage, size_t cap, hipStream_t s);
+// Replace every spin by the host bytes (L x L, nonzero = up), staged through
+// `stage` (cap bytes >= L); synchronises the stream.
+int write_spins(uint64_t* W, const Geometry& g, const uint8_t* host, uint8_t* stage, size_t cap, hipStream_t s);
 
 }  // namespace ising

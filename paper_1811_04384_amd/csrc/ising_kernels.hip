@@ -310,8 +310,14 @@ __global__ void __launch_bounds__(kResidentMaxBlock)
         __syncthreads();
     }
     uint64_t* __restrict__ W = IN_LDS ? lds_words : G;
-    auto ld = [&](int i, int j) { return W[i * L + j]; };
-    auto st = [&](int i, int j, uint64_t v) { W[i * L + j] = v; };
+    // word offsets: 32-bit inside LDS, 64-bit in global memory (N L may
+    // exceed 2^31 words there)
+    auto off = [&](int i, int j) {
+        if constexpr (IN_LDS) return (uint32_t)i * (uint32_t)L + (uint32_t)j;
+        else return (size_t)i * (size_t)L + (size_t)j;
+    };
+    auto ld = [&](int i, int j) { return W[off(i, j)]; };
+    auto st = [&](int i, int j, uint64_t v) { W[off(i, j)] = v; };
     const int segs = (L + 2 * WPT - 1) / (2 * WPT);
     const uint32_t units = (uint32_t)N * (uint32_t)segs;
     const uint64_t t0 = state.t;
@@ -438,18 +444,21 @@ __global__ void __launch_bounds__(256) k_unpack(const uint64_t* __restrict__ W, 
     out[idx] = (uint8_t)((W[(size_t)I * g.L + c] >> (3 * (20 - p))) & 1ull);
 }
 
-__global__ void __launch_bounds__(256) k_pack(const uint8_t* __restrict__ in, Geometry g, uint64_t* __restrict__ W) {
-    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t n_words = (uint32_t)g.N * (uint32_t)g.L;
-    if (idx >= n_words) return;
-    const int I = (int)(idx / (uint32_t)g.L);
-    const int J = (int)(idx - (uint32_t)I * (uint32_t)g.L);
-    uint64_t v = 0;
-    for (int p = 0; p < 21; ++p) {
-        const int64_t r = (int64_t)I + (int64_t)p * g.N;
-        if (r < g.L && in[(size_t)r * g.L + J]) v |= 1ull << (3 * (20 - p));
-    }
-    W[idx] = v;
+// Write nrows lattice rows r0 .. r0 + nrows - 1 (row-major bytes, nonzero =
+// up) into their words: row r is position r div N of word row r mod N.  With
+// nrows <= N every word is touched by one row at most, so the bit updates of
+// one launch never share a word.
+__global__ void __launch_bounds__(256) k_pack_rows(const uint8_t* __restrict__ in, Geometry g, int32_t r0,
+                                                   int32_t nrows, uint64_t* __restrict__ W) {
+    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (uint64_t)nrows * (uint64_t)g.L) return;
+    const int i = (int)(idx / (uint64_t)g.L);
+    const int c = (int)(idx - (uint64_t)i * (uint64_t)g.L);
+    const int r = r0 + i;
+    const int I = r % g.N, p = r / g.N;
+    const uint64_t bit = 1ull << (3 * (20 - p));
+    uint64_t* w = W + ((size_t)I * g.L + c);
+    *w = in[idx] ? (*w | bit) : (*w & ~bit);
 }
 
 inline unsigned grid_for(uint64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -530,9 +539,11 @@ hipError_t launch_unpack(const uint64_t* W, const Geometry& g, int32_t r0, int32
     return hipGetLastError();
 }
 
-hipError_t launch_pack(const uint8_t* in, const Geometry& g, uint64_t* W, hipStream_t s) {
-    const uint64_t n = (uint64_t)g.N * (uint64_t)g.L;
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(n, 256)), dim3(256), 0, s, in, g, W);
+hipError_t launch_pack_rows(const uint8_t* in, const Geometry& g, int32_t r0, int32_t nrows, uint64_t* W,
+                            hipStream_t s) {
+    if (nrows < 1 || nrows > g.N || r0 < 0 || r0 + nrows > g.L) return hipErrorInvalidValue;
+    const uint64_t n = (uint64_t)nrows * (uint64_t)g.L;
+    hipLaunchKernelGGL(k_pack_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, in, g, r0, nrows, W);
     return hipGetLastError();
 }
 

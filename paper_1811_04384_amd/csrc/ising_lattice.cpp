@@ -29,12 +29,44 @@ struct ising_lattice {
     void* d_fin = nullptr;    // device scratch of the partial-sum reduction
     uint32_t* strip_pos = nullptr;    // drawn picks of the strip dynamics (allocated on first use)
     uint64_t* strip_codes = nullptr;  // their acceptance codes
+    uint8_t* d_stage = nullptr;       // spin input/output staging, spin_stage_bytes(L)
+    Moments* d_scan = nullptr;        // moment sums of up to kScanBlock temperatures of a scan
 };
+
+// Temperatures of a scan whose moment sums are read back together.
+constexpr int32_t kScanBlock = 256;
 
 namespace ising {
 std::string& last_error_ref() {
     thread_local std::string s;
     return s;
+}
+
+int read_spin_window(const uint64_t* W, const Geometry& g, int32_t r0, int32_t c0, int32_t nrows, int32_t ncols,
+                     uint8_t* host, uint8_t* stage, size_t cap, hipStream_t s) {
+    const int32_t chunk = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)nrows, cap / (size_t)ncols));
+    for (int32_t i0 = 0; i0 < nrows; i0 += chunk) {
+        const int32_t nr = std::min(chunk, nrows - i0);
+        const int32_t r = (int32_t)(((int64_t)r0 + i0) % g.L);
+        ISING_HIP(launch_unpack(W, g, r, c0, nr, ncols, stage, s));
+        ISING_HIP(hipMemcpyAsync(host + (size_t)i0 * (size_t)ncols, stage, (size_t)nr * (size_t)ncols,
+                                 hipMemcpyDeviceToHost, s));
+    }
+    ISING_HIP(hipStreamSynchronize(s));
+    return ISING_OK;
+}
+
+int write_spins(uint64_t* W, const Geometry& g, const uint8_t* host, uint8_t* stage, size_t cap, hipStream_t s) {
+    // at most N rows per piece, so that no word is written by two rows of one launch
+    const int32_t chunk = (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)g.N, cap / (size_t)g.L));
+    for (int32_t r0 = 0; r0 < g.L; r0 += chunk) {
+        const int32_t nr = std::min(chunk, g.L - r0);
+        ISING_HIP(hipMemcpyAsync(stage, host + (size_t)r0 * (size_t)g.L, (size_t)nr * (size_t)g.L,
+                                 hipMemcpyHostToDevice, s));
+        ISING_HIP(launch_pack_rows(stage, g, r0, nr, W, s));
+    }
+    ISING_HIP(hipStreamSynchronize(s));
+    return ISING_OK;
 }
 }  // namespace ising
 
@@ -78,6 +110,8 @@ static void release(ising_lattice* h) {
     if (h->d_fin) (void)hipFree(h->d_fin);
     if (h->strip_pos) (void)hipFree(h->strip_pos);
     if (h->strip_codes) (void)hipFree(h->strip_codes);
+    if (h->d_stage) (void)hipFree(h->d_stage);
+    if (h->d_scan) (void)hipFree(h->d_scan);
     delete h;
 }
 
@@ -117,6 +151,8 @@ static int create_impl(int32_t L, uint64_t seed, int32_t init, void* dev_words, 
     e = hipMalloc(&h->partials, (size_t)h->partial_cap * sizeof(Partial));
     if (e == hipSuccess) e = hipMalloc(&h->d_EM, 2 * sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc(&h->d_fin, finalize_scratch_bytes());
+    if (e == hipSuccess) e = hipMalloc(&h->d_stage, spin_stage_bytes(L));
+    if (e == hipSuccess) e = hipMalloc(&h->d_scan, sizeof(Moments) * kScanBlock);
     if (e == hipSuccess) e = hipMemsetAsync(h->d_fin, 0, finalize_scratch_bytes(), h->stream);
     if (e != hipSuccess) {
         release(h);
@@ -237,24 +273,23 @@ int ising_scan(ising_lattice* h, int32_t n_T, const double* T, int64_t therm, in
     if (!T || !out) return fail(ISING_EINVAL, "ising_scan: null array");
     for (int32_t i = 0; i < n_T; ++i)
         if (!valid_T(T[i])) return fail(ISING_EINVAL, "ising_scan: T[%d] = %g is not finite and > 0", i, T[i]);
-    Moments* d = nullptr;
-    ISING_HIP(hipMalloc(&d, sizeof(Moments) * (size_t)n_T));
-    hipError_t e = hipMemsetAsync(d, 0, sizeof(Moments) * (size_t)n_T, h->stream);
-    int rc = e == hipSuccess ? ISING_OK : hip_fail(e, "hipMemsetAsync");
-    for (int32_t i = 0; i < n_T && rc == ISING_OK; ++i) {
-        rc = sweep_impl(h, T[i], therm, 0, nullptr, nullptr);
-        if (rc == ISING_OK) rc = sweep_impl(h, T[i], meas, every, nullptr, nullptr, d + i);
+    // blocks of up to kScanBlock temperatures accumulate into the handle's
+    // moment array and are read back together
+    for (int32_t j0 = 0; j0 < n_T; j0 += kScanBlock) {
+        const int32_t nb = std::min(kScanBlock, n_T - j0);
+        ISING_HIP(hipMemsetAsync(h->d_scan, 0, sizeof(Moments) * (size_t)nb, h->stream));
+        for (int32_t i = 0; i < nb; ++i) {
+            int rc = sweep_impl(h, T[j0 + i], therm, 0, nullptr, nullptr);
+            if (rc == ISING_OK) rc = sweep_impl(h, T[j0 + i], meas, every, nullptr, nullptr, h->d_scan + i);
+            if (rc != ISING_OK) {
+                (void)hipStreamSynchronize(h->stream);
+                return rc;
+            }
+        }
+        ISING_HIP(hipMemcpyAsync(out + j0, h->d_scan, sizeof(Moments) * (size_t)nb, hipMemcpyDeviceToHost, h->stream));
+        ISING_HIP(hipStreamSynchronize(h->stream));
     }
-    if (rc == ISING_OK) {
-        e = hipMemcpyAsync(out, d, sizeof(Moments) * (size_t)n_T, hipMemcpyDeviceToHost, h->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) rc = hip_fail(e, "ising_scan read-back");
-    } else {
-        (void)hipStreamSynchronize(h->stream);
-    }
-    e = hipFree(d);
-    if (rc == ISING_OK && e != hipSuccess) rc = hip_fail(e, "hipFree");
-    return rc;
+    return ISING_OK;
 }
 
 // Largest number of picks one strip may apply in one phase (bounds the run
@@ -384,16 +419,7 @@ int ising_get_spins_region(ising_lattice* h, int32_t r0, int32_t c0, int32_t nro
     if (nrows < 1 || ncols < 1 || nrows > L || ncols > L)
         return fail(ISING_EINVAL, "ising_get_spins_region: window %dx%d outside 1..L=%d", nrows, ncols, L);
     const int32_t rr = (int32_t)(((int64_t)r0 % L + L) % L), cc = (int32_t)(((int64_t)c0 % L + L) % L);
-    const size_t bytes = (size_t)nrows * (size_t)ncols;
-    uint8_t* d = nullptr;
-    ISING_HIP(hipMalloc(&d, bytes));
-    hipError_t e = launch_unpack(h->W, h->g, rr, cc, nrows, ncols, d, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    hipError_t e2 = hipFree(d);
-    if (e != hipSuccess) return hip_fail(e, "ising_get_spins_region");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
-    return ISING_OK;
+    return read_spin_window(h->W, h->g, rr, cc, nrows, ncols, host, h->d_stage, spin_stage_bytes(L), h->stream);
 }
 
 int ising_get_spins(ising_lattice* h, uint8_t* host) {
@@ -403,16 +429,7 @@ int ising_get_spins(ising_lattice* h, uint8_t* host) {
 
 int ising_set_spins(ising_lattice* h, const uint8_t* host) {
     if (!h || !host) return fail(ISING_EINVAL, "ising_set_spins: null argument");
-    const size_t bytes = (size_t)h->g.L * (size_t)h->g.L;
-    uint8_t* d = nullptr;
-    ISING_HIP(hipMalloc(&d, bytes));
-    hipError_t e = hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = launch_pack(d, h->g, h->W, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    hipError_t e2 = hipFree(d);
-    if (e != hipSuccess) return hip_fail(e, "ising_set_spins");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
-    return ISING_OK;
+    return write_spins(h->W, h->g, host, h->d_stage, spin_stage_bytes(h->g.L), h->stream);
 }
 
 int ising_get_sweep_count(ising_lattice* h, uint64_t* t) {

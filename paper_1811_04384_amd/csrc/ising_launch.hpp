@@ -66,11 +66,12 @@ hipError_t launch_observe_single(const uint64_t* W, const Geometry& g, Partial* 
                                  hipStream_t s);
 int64_t observe_single_waves(const Geometry& g);
 
-// Unpack an nrows x ncols window (indices mod L) to bytes; pack a full byte
-// lattice into words.
+// Unpack an nrows x ncols window (indices mod L) to bytes; write the bytes
+// of lattice rows r0 .. r0 + nrows - 1 (1 <= nrows <= N) into their words.
 hipError_t launch_unpack(const uint64_t* W, const Geometry& g, int32_t r0, int32_t c0, int32_t nrows,
                          int32_t ncols, uint8_t* out, hipStream_t s);
-hipError_t launch_pack(const uint8_t* in, const Geometry& g, uint64_t* W, hipStream_t s);
+hipError_t launch_pack_rows(const uint8_t* in, const Geometry& g, int32_t r0, int32_t nrows, uint64_t* W,
+                            hipStream_t s);
 
 // ---- batches --------------------------------------------------------------
 

@@ -2,6 +2,7 @@
 // word lattice, replica k at its own temperature (see ising_replicas.hip).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <new>
 
 #include "ising_host.hpp"
@@ -18,6 +19,7 @@ struct ising_replicas {
     int wpt = 2;
     unsigned long long* d_totals = nullptr;  // 42 counters of the observables reduction
     int64_t* d_EM = nullptr;                 // E[21], M[21] of ising_replicas_observables
+    uint8_t* d_stage = nullptr;              // spin output staging, spin_stage_bytes(L)
 };
 
 namespace {
@@ -27,6 +29,7 @@ void release(ising_replicas* h) {
     if (h->W) (void)hipFree(h->W);
     if (h->d_totals) (void)hipFree(h->d_totals);
     if (h->d_EM) (void)hipFree(h->d_EM);
+    if (h->d_stage) (void)hipFree(h->d_stage);
     delete h;
 }
 
@@ -84,6 +87,7 @@ int ising_replicas_create(int32_t L, uint64_t seed, int32_t init, void* stream, 
     hipError_t e = hipMalloc(&h->W, sizeof(uint64_t) * (size_t)L * (size_t)L);
     if (e == hipSuccess) e = hipMalloc(&h->d_totals, sizeof(unsigned long long) * 2 * kReplicas);
     if (e == hipSuccess) e = hipMalloc(&h->d_EM, sizeof(int64_t) * 2 * kReplicas);
+    if (e == hipSuccess) e = hipMalloc(&h->d_stage, spin_stage_bytes(L));
     if (e == hipSuccess) e = hipMemsetAsync(h->d_totals, 0, sizeof(unsigned long long) * 2 * kReplicas, h->stream);
     if (e == hipSuccess) e = launch_replica_init(h->W, L, seed, init == ISING_HOT, h->stream);
     if (e != hipSuccess) {
@@ -137,15 +141,15 @@ int ising_replicas_observables(ising_replicas* h, int64_t* E, int64_t* M) {
 int ising_replicas_get_spins(ising_replicas* h, int32_t k, uint8_t* host) {
     if (!h || !host) return fail(ISING_EINVAL, "ising_replicas_get_spins: null argument");
     if (k < 0 || k >= kReplicas) return fail(ISING_EINVAL, "ising_replicas_get_spins: replica %d out of range", k);
-    const size_t bytes = (size_t)h->L * (size_t)h->L;
-    uint8_t* d = nullptr;
-    ISING_HIP(hipMalloc(&d, bytes));
-    hipError_t e = launch_replica_unpack(h->W, h->L, k, d, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    hipError_t e2 = hipFree(d);
-    if (e != hipSuccess) return hip_fail(e, "ising_replicas_get_spins");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
+    const int32_t L = h->L;
+    const int32_t chunk = (int32_t)std::max<size_t>(1, spin_stage_bytes(L) / (size_t)L);
+    for (int32_t r0 = 0; r0 < L; r0 += chunk) {
+        const int32_t nr = std::min(chunk, L - r0);
+        ISING_HIP(launch_replica_unpack(h->W, L, k, r0, nr, h->d_stage, h->stream));
+        ISING_HIP(hipMemcpyAsync(host + (size_t)r0 * (size_t)L, h->d_stage, (size_t)nr * (size_t)L,
+                                 hipMemcpyDeviceToHost, h->stream));
+    }
+    ISING_HIP(hipStreamSynchronize(h->stream));
     return ISING_OK;
 }
 

@@ -180,11 +180,12 @@ __global__ void k_replica_finalize(unsigned long long* __restrict__ totals, int 
     totals[kReplicas + k] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_replica_unpack(const uint64_t* __restrict__ W, int L, int k,
-                                                       uint8_t* __restrict__ out) {
+// Spins of replica k in rows r0 .. r0 + nrows - 1, row major.
+__global__ void __launch_bounds__(256) k_replica_unpack(const uint64_t* __restrict__ W, int L, int k, int r0,
+                                                       int nrows, uint8_t* __restrict__ out) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (uint64_t)L * (uint64_t)L) return;
-    out[i] = (uint8_t)((W[i] >> (3 * (20 - k))) & 1u);
+    if (i >= (uint64_t)nrows * (uint64_t)L) return;
+    out[i] = (uint8_t)((W[(uint64_t)r0 * (uint64_t)L + i] >> (3 * (20 - k))) & 1u);
 }
 
 inline unsigned rgrid(uint64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -218,8 +219,10 @@ hipError_t launch_replica_observe(const uint64_t* W, int L, unsigned long long* 
     return hipGetLastError();
 }
 
-hipError_t launch_replica_unpack(const uint64_t* W, int L, int k, uint8_t* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_replica_unpack, dim3(rgrid((uint64_t)L * L, 256)), dim3(256), 0, s, W, L, k, out);
+hipError_t launch_replica_unpack(const uint64_t* W, int L, int k, int r0, int nrows, uint8_t* out, hipStream_t s) {
+    if (r0 < 0 || nrows < 1 || r0 + nrows > L) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_replica_unpack, dim3(rgrid((uint64_t)nrows * L, 256)), dim3(256), 0, s, W, L, k, r0, nrows,
+                       out);
     return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ hipError_t launch_replica_halfsweep(int wpt, uint64_t* W, const ReplicaArgs& a, 
 // 42 zeroed unsigned 64-bit counters, left zeroed.
 hipError_t launch_replica_observe(const uint64_t* W, int L, unsigned long long* totals, int64_t* series_E,
                                   int64_t* series_M, int64_t idx, Moments* mom, int64_t* out_EM, hipStream_t s);
-hipError_t launch_replica_unpack(const uint64_t* W, int L, int k, uint8_t* out, hipStream_t s);
+// Spins of replica k in rows r0 .. r0 + nrows - 1 as bytes (row major).
+hipError_t launch_replica_unpack(const uint64_t* W, int L, int k, int r0, int nrows, uint8_t* out, hipStream_t s);
 
 }  // namespace ising

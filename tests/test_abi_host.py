@@ -41,12 +41,13 @@ def test_library_was_built_from_these_sources():
 
 
 def test_instruction_rate_microbenchmark_is_built():
-    # built beside the library by the same build step; bench.py --valu-rates runs it
-    from paper_1811_04384_amd.build import VALU_RATES
+    # a program of the benchmark, built beside bench.py (not by the library's
+    # build); bench.py --valu-rates runs it
+    from bench import VALU_RATES, VALU_RATES_SRC
 
     assert os.path.isfile(VALU_RATES) and os.access(VALU_RATES, os.X_OK)
-    assert os.path.getmtime(VALU_RATES) >= os.path.getmtime(
-        os.path.join(ROOT, "paper_1811_04384_amd", "csrc", "valu_rates.hip"))
+    assert os.path.getmtime(VALU_RATES) >= os.path.getmtime(VALU_RATES_SRC)
+    assert not os.path.exists(os.path.join(ROOT, "paper_1811_04384_amd", "valu_rates"))
 
 
 def test_geometry_matches_oracle():
@@ -126,3 +127,20 @@ def test_moment_calls_reject_bad_arguments_without_a_gpu():
     assert lib.ising_batch_scan(None, 1, None, 0, 1, 1, None) == ising.ISING_EINVAL
     assert lib.ising_sweep_moments(None, 2.0, 1, 1, None) == ising.ISING_EINVAL
     assert lib.ising_batch_moments(None, None) == ising.ISING_EINVAL
+
+
+def test_batch_plan_check_bounds_resident_lattices():
+    # one workgroup per lattice is refused for sizes far beyond one
+    # workgroup's LDS (a 2^18 lattice is 26 GB and its word offsets need 64
+    # bits), before any batch or GPU exists
+    ok = dict(resident_max_L=4096, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=50)
+    ising.ising_batch_check_plan(ok)
+    for bad in (dict(ok, resident_max_L=1 << 18), dict(ok, resident_max_L=4098), dict(ok, resident_max_L=-2),
+                dict(ok, words_per_thread=3), dict(ok, tiled_block=96), dict(ok, resident_block=2048),
+                dict(ok, sweeps_per_graph=0)):
+        with pytest.raises(ising.IsingError) as e:
+            ising.ising_batch_check_plan(bad)
+        assert e.value.code == ising.ISING_EINVAL
+    with pytest.raises(ising.IsingError):
+        ising.ising_batch_check_plan(dict(ok, resident_max_L=1 << 18))
+    assert "resident_max_L" in ising.ising_last_error()

@@ -6,7 +6,7 @@ import subprocess
 
 import pytest
 
-from paper_1811_04384_amd.build import VALU_RATES
+from bench import VALU_RATES
 
 pytestmark = pytest.mark.gpu
 

@@ -64,6 +64,48 @@ def test_served_results_equal_alone():
         srv.close()
 
 
+def test_served_config5_shapes_equal_alone():
+    """Requests of the served workload's shapes -- L = 2^U{7..12} (128 ..
+    4096), T ~ U[1.5, 3.5], hot start, seed = request id -- with 1000 to 3000
+    sweeps each, so that every request spans many 100-sweep quanta; 32
+    requests share 8 slots and arrive two per quantum while others run.
+    Every served E, M equals the request run alone on the single-lattice
+    path, and the oracle's for L <= 256."""
+    rng = np.random.default_rng(2026)
+    reqs = []
+    for rid in range(32):
+        L = int(2 ** rng.integers(7, 13))
+        T = float(rng.uniform(1.5, 3.5))
+        sweeps = int(rng.integers(1000, 3001))
+        reqs.append((rid, L, T, sweeps))
+    assert {L for _, L, _, _ in reqs} == {128, 256, 512, 1024, 2048, 4096}
+    srv = ising.Server(hbm_budget=1 << 30, max_slots=8, quantum_sweeps=100)
+    try:
+        results, pending, steps, max_resident = {}, list(reqs), 0, 0
+        while len(results) < len(reqs):
+            for _ in range(2):
+                if pending:
+                    rid, L, T, sw = pending.pop(0)
+                    srv.submit(rid, L, T, sw)
+            srv.step()
+            max_resident = max(max_resident, srv.stats()["resident"])
+            for r in srv.poll():
+                results[r["req_id"]] = r
+            steps += 1
+            assert steps < 100000
+        assert max_resident == 8
+        for rid, L, T, sw in reqs:
+            r = results[rid]
+            assert r["status"] == 0 and r["L"] == L and r["sweeps"] == sw
+            assert (r["E"], r["M"]) == _alone(L, T, sw, rid), rid
+            if L <= 256:
+                s = oracle.init(L, rid, True)
+                oracle.sweep(s, rid, 0, sw, T)
+                assert (r["E"], r["M"]) == oracle.observables(s), rid
+    finally:
+        srv.close()
+
+
 def test_admission_by_memory_budget():
     L = 512
     per = ising.ising_required_bytes(L)  # 106496 bytes

@@ -256,3 +256,51 @@ def test_largest_lattice_matches_oracle():
             assert (got == want).all(), (r, c)
     finally:
         lat.close()
+
+
+def test_outputs_on_a_non_default_stream_are_ordered():
+    """A lattice on a stream of its own: the series tensors (allocated on
+    torch's stream, written by the library on the lattice's) read at once on
+    torch's stream, and an accumulator zeroed on torch's stream and filled on
+    the lattice's, both equal the oracle -- the binding orders the two
+    streams around each call."""
+    import torch
+
+    L, seed, T = 1008, 3, 2.4
+    side = torch.cuda.Stream()
+    lat = ising.Lattice(L, seed, hot=True, stream=side)
+    try:
+        E, M = lat.sweep_measure(T, 40, 4)
+        got_E, got_M = E.cpu().numpy().tolist(), M.cpu().numpy().tolist()
+        acc = lat.sweep_moments(T, 20, 2)
+        got_m = ising.moments_of(acc)
+        got_s = lat.spins()
+    finally:
+        lat.close()
+    ref = oracle.init(L, seed, True)
+    Es, Ms = oracle.sweep(ref, seed, 0, 40, T, every=4)
+    Es2, Ms2 = oracle.sweep(ref, seed, 40, 20, T, every=2)
+    assert got_E == Es.tolist() and got_M == Ms.tolist()
+    assert got_m == oracle.moments(Es2, Ms2)
+    assert (got_s == ref).all()
+
+
+def test_spin_io_in_pieces_through_the_staging_buffer():
+    """Spin reads and writes move through a fixed 16 MiB staging buffer:
+    at L = 8192 (64 MiB of bytes) a full read, a window that wraps in both
+    directions and a full write all take several pieces and stay exact."""
+    L, seed = 8192, 17
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        ref = oracle.init(L, seed, True)
+        assert (lat.spins() == ref).all()
+        win = lat.region(L - 3000, L - 5, 5000, 11)
+        want = np.roll(np.roll(ref, 3000, axis=0), 5, axis=1)[:5000, :11]
+        assert (win == want).all()
+        rng = np.random.default_rng(5)
+        s = (rng.random((L, L)) < 0.3).astype(np.uint8)
+        lat.set_spins(s)
+        assert (lat.spins() == s).all()
+        assert lat.observables() == oracle.observables(s)
+    finally:
+        lat.close()

@@ -11,7 +11,11 @@
   and 512 over all 500 samples and the final state, L = 1024 and 2048 over
   the first 50 samples (their full oracle run would take minutes); four
   L = 256 lattices stay equal over 500 sweeps.
-- The L = 32768 single lattice over 20 sweeps on oracle-evolved windows.
+- The L = 32768 single lattice over 20 sweeps on oracle-evolved windows, and
+  the whole L = 32768 lattice of the headline workload (hot start, seed 11,
+  T = 2.269, the benchmark's launch configuration) after 2 sweeps: every
+  sampled E and M (Section 5.3's bond energy) and every one of its 1.07e9
+  spins equal a full oracle run.
 """
 import time
 
@@ -176,3 +180,32 @@ def test_server_zero_sweep_and_cold_requests():
         assert srv.stats() == {"queued": 0, "resident": 0, "finished": 0, "bytes_in_use": 0}
     finally:
         srv.close()
+
+
+def test_l32768_full_lattice_matches_oracle():
+    """The headline lattice end to end: E and M after each of 2 sweeps (the
+    fused reduction), E and M of the final state (the standalone one), and
+    the full final state, against a full oracle run of the same chain (about
+    ten seconds on the host's cores, 1 GiB of bytes)."""
+    import torch
+
+    L, seed, T, n = 32768, 11, 2.269, 2
+    print("L=32768 full oracle run", flush=True)
+    ref = oracle.init(L, seed, True)
+    Es, Ms = oracle.sweep(ref, seed, 0, n, T, every=1)
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        print("L=32768 GPU run, plan", lat.plan(), flush=True)
+        E, M = lat.sweep_measure(T, n, 1)
+        torch.cuda.synchronize()
+        assert E.cpu().numpy().tolist() == Es.tolist() and M.cpu().numpy().tolist() == Ms.tolist()
+        assert lat.observables() == oracle.observables(ref) == (int(Es[-1]), int(Ms[-1]))
+        got = lat.spins()
+        assert got.shape == ref.shape
+        rows_got = got.sum(axis=1, dtype=np.int64)
+        rows_want = ref.sum(axis=1, dtype=np.int64)
+        bad_rows = np.nonzero(rows_got != rows_want)[0]
+        assert bad_rows.size == 0, bad_rows[:10]
+        assert np.array_equal(got, ref)
+    finally:
+        lat.close()
