@@ -242,6 +242,37 @@ int ising_words(ising_lattice* h, void** dev_words, size_t* bytes);
 int ising_set_plan(ising_lattice* h, int32_t words_per_thread, int32_t block);
 int ising_get_plan(ising_lattice* h, int32_t* words_per_thread, int32_t* block);
 
+/* Several sweeps per launch on LDS tiles (the paper's sub-lattices with
+   ghost columns, Sections 4 and 5.2, Figs. 3 and 5, as redundant halos):
+   with sweeps_per_launch = K in [1, 16], ising_sweep* runs K sweeps per
+   launch, each workgroup on one tile -- every word row of tile_cols interior
+   word columns (even) plus 2K halo columns on each side, all in LDS -- and
+   K = 0 goes back to one launch per half-sweep.  tile_cols >= L keeps the
+   whole lattice in one workgroup; otherwise tile_cols + 4K <= L.  block:
+   threads per workgroup, a multiple of 64 in [64, 1024].  EINVAL if a tile
+   does not fit in LDS.  Synchronises the stream.  Results never depend on
+   it.  Setting it switches resident tiles off.  ising_get_tiling returns
+   K = 0 (and zeros) when tiling is off. */
+int ising_set_tiling(ising_lattice* h, int32_t sweeps_per_launch, int32_t tile_cols, int32_t block);
+int ising_get_tiling(ising_lattice* h, int32_t* sweeps_per_launch, int32_t* tile_cols, int32_t* block);
+
+/* Resident tiles (the paper's decomposition into vertical strips with
+   ghost columns, Sections 4 and 5.2, Figs. 3 and 5, on the workgroups of one
+   GPU): with tile_cols > 0, ising_sweep* keeps every word row of tile_cols
+   word columns (even) in one workgroup's LDS, for up to max_sweeps
+   (1..4096) sweeps per launch, and each half-sweep trades the tiles'
+   boundary words with the neighbouring tiles through global memory;
+   tile_cols >= L keeps the whole lattice in one workgroup.  block: threads
+   per workgroup, a multiple of 64 in [64, 1024].  tile_cols = 0 switches it
+   off; either this or ising_set_tiling is in effect, the last one set.
+   EINVAL if a tile does not fit in LDS or the tiles do not all fit on the
+   device at once.  A launch whose tiles wait for a neighbour longer than
+   about a second is abandoned: the next call on the handle returns
+   ISING_EHIP, and the lattice state is undefined.  Synchronises.  Results
+   never depend on it.  ising_get_resident_tiles returns zeros when off. */
+int ising_set_resident_tiles(ising_lattice* h, int32_t tile_cols, int32_t block, int32_t max_sweeps);
+int ising_get_resident_tiles(ising_lattice* h, int32_t* tile_cols, int32_t* block, int32_t* max_sweeps);
+
 /* Time every plan on this lattice's shape (on a scratch copy, the state is
    not touched) and keep the fastest.  Synchronises.  best_ms (host, may be
    NULL) receives the time per sweep of the chosen plan. */
@@ -302,23 +333,32 @@ int ising_batch_get_sweep_count(ising_batch* b, int32_t i, uint64_t* t);
 
 /* Execution plan.  Lattices with L <= resident_max_L are advanced by one
    workgroup each, all their sweeps of a chunk inside one launch, the lattice
-   held in LDS when it fits; the others by per-half-sweep launches over a
-   table of (lattice, row segment) work items with words_per_thread words per
-   thread.  sweeps_per_graph sweeps are captured in one hipGraph (rounded to
-   a multiple of `every`).  Results never depend on the plan. */
+   held in LDS when it fits; lattices with resident_max_L < L <= tile_max_L
+   by multi-sweep LDS tiles (tile_sweeps sweeps per launch on tiles of
+   tile_cols word columns with redundant halos, as ising_set_tiling; a
+   lattice whose tile would not fit in LDS goes to the next path); the others
+   by per-half-sweep launches over a table of (lattice, row segment) work
+   items with words_per_thread words per thread.  sweeps_per_graph sweeps are
+   captured in one hipGraph (rounded to a multiple of `every`).  Results
+   never depend on the plan. */
 typedef struct {
     int32_t resident_max_L;   /* 0 = no resident lattices                    */
     int32_t resident_block;   /* threads per resident workgroup (64..1024)   */
-    int32_t words_per_thread; /* 1, 2 or 4 (tiled path)                      */
-    int32_t tiled_block;      /* threads per tiled workgroup (64..1024)      */
+    int32_t words_per_thread; /* 1, 2 or 4 (half-sweep path)                 */
+    int32_t tiled_block;      /* threads per half-sweep workgroup (64..256)  */
     int32_t sweeps_per_graph; /* >= 1                                        */
+    int32_t tile_max_L;       /* 0 = no multi-sweep tiles                    */
+    int32_t tile_sweeps;      /* sweeps per tile launch, 1..16               */
+    int32_t tile_cols;        /* interior word columns per tile (even)       */
+    int32_t tile_block;       /* threads per tile workgroup (64..1024)       */
 } ising_batch_plan;
 
 /* Validate a plan without a batch (host only, no GPU needed): ISING_OK or
    EINVAL with the reason.  resident_max_L must be in [0, 4096]: one
    workgroup per lattice is only sensible for lattices that fit, or nearly
-   fit, in one workgroup's LDS.  ising_batch_set_plan applies the same
-   checks. */
+   fit, in one workgroup's LDS.  With tile_max_L > 0, tile_sweeps must be in
+   [1, 16], tile_cols even and >= 2, tile_block a multiple of 64 in
+   [64, 1024].  ising_batch_set_plan applies the same checks. */
 int ising_batch_check_plan(const ising_batch_plan* plan);
 int ising_batch_set_plan(ising_batch* b, const ising_batch_plan* plan);
 int ising_batch_get_plan(ising_batch* b, ising_batch_plan* plan);

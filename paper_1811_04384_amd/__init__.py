@@ -268,6 +268,26 @@ def ising_autotune(h, T):
     return float(ms.value)
 
 
+def ising_set_tiling(h, sweeps_per_launch, tile_cols=0, block=256):
+    _check(_lib.load().ising_set_tiling(h, int(sweeps_per_launch), int(tile_cols), int(block)))
+
+
+def ising_get_tiling(h):
+    k, c, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.load().ising_get_tiling(h, ctypes.byref(k), ctypes.byref(c), ctypes.byref(b)))
+    return int(k.value), int(c.value), int(b.value)
+
+
+def ising_set_resident_tiles(h, tile_cols, block=512, max_sweeps=1000):
+    _check(_lib.load().ising_set_resident_tiles(h, int(tile_cols), int(block), int(max_sweeps)))
+
+
+def ising_get_resident_tiles(h):
+    c, b, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.load().ising_get_resident_tiles(h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(k)))
+    return int(c.value), int(b.value), int(k.value)
+
+
 def ising_synchronize(h):
     _check(_lib.load().ising_synchronize(h))
 
@@ -551,6 +571,18 @@ class Lattice:
 
     def plan(self):
         return ising_get_plan(self.handle)
+
+    def set_tiling(self, sweeps_per_launch, tile_cols=0, block=256):
+        ising_set_tiling(self.handle, sweeps_per_launch, tile_cols, block)
+
+    def tiling(self):
+        return ising_get_tiling(self.handle)
+
+    def set_resident_tiles(self, tile_cols, block=512, max_sweeps=1000):
+        ising_set_resident_tiles(self.handle, tile_cols, block, max_sweeps)
+
+    def resident_tiles(self):
+        return ising_get_resident_tiles(self.handle)
 
     def autotune(self, T):
         return ising_autotune(self.handle, T)

@@ -16,7 +16,8 @@ ISING_COLD, ISING_HOT = 0, 1
 
 class BatchPlan(ctypes.Structure):
     _fields_ = [("resident_max_L", c_i32), ("resident_block", c_i32), ("words_per_thread", c_i32),
-                ("tiled_block", c_i32), ("sweeps_per_graph", c_i32)]
+                ("tiled_block", c_i32), ("sweeps_per_graph", c_i32), ("tile_max_L", c_i32), ("tile_sweeps", c_i32),
+                ("tile_cols", c_i32), ("tile_block", c_i32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -69,6 +70,10 @@ SIGNATURES = {
     "ising_get_sweep_count": (c_int, [c_vp, P(c_u64)]),
     "ising_set_sweep_count": (c_int, [c_vp, c_u64]),
     "ising_words": (c_int, [c_vp, P(c_vp), P(c_sz)]),
+    "ising_set_tiling": (c_int, [c_vp, c_i32, c_i32, c_i32]),
+    "ising_get_tiling": (c_int, [c_vp, P(c_i32), P(c_i32), P(c_i32)]),
+    "ising_set_resident_tiles": (c_int, [c_vp, c_i32, c_i32, c_i32]),
+    "ising_get_resident_tiles": (c_int, [c_vp, P(c_i32), P(c_i32), P(c_i32)]),
     "ising_set_plan": (c_int, [c_vp, c_i32, c_i32]),
     "ising_get_plan": (c_int, [c_vp, P(c_i32), P(c_i32)]),
     "ising_autotune": (c_int, [c_vp, c_dbl, P(c_dbl)]),

@@ -1,15 +1,20 @@
 // Batch engine: many independent lattices of mixed L and T advanced together.
 //
-// Two execution paths, chosen per lattice by the plan (results never depend
+// Three execution paths, chosen per lattice by the plan (results never depend
 // on it because every random number is a function of (seed, sweep, site)):
-//  - tiled: per half-sweep, one launch over a table of wavefronts covering
-//    every tiled lattice (each wavefront belongs to one lattice);
+//  - half-sweep launches: per half-sweep, one launch over a table of
+//    wavefronts covering every such lattice (each wavefront belongs to one
+//    lattice);
 //  - resident: one workgroup per lattice runs all sweeps of a chunk inside
 //    one launch, colours separated by workgroup barriers, the lattice kept in
-//    LDS when it fits.
-// A chunk of sweeps is captured once into a hipGraph (resident and tiled
-// work as parallel branches) and replayed; per-call parameters live in
-// device memory so replays need no re-capture.
+//    LDS when it fits;
+//  - multi-sweep tiles: several sweeps per launch on LDS tiles of word
+//    columns with redundant halos, one workgroup per tile, tiles of all such
+//    lattices in one launch.
+// A chunk of sweeps is captured once into a hipGraph (the half-sweep
+// launches on one branch, resident and tile work on the other) and
+// replayed; per-call parameters live in device memory so replays need no
+// re-capture.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,7 +53,7 @@ struct ising_batch {
     std::vector<uint64_t> t_host;
     ising_batch_plan plan{};
     // derived from the plan
-    std::vector<int32_t> resident;  // 0 tiled, 1 resident in LDS, 2 resident in global memory
+    std::vector<int32_t> resident;  // 0 half-sweep launches, 1 resident in LDS, 2 resident in global memory, 3 tiles
     std::vector<int64_t> units;
     std::vector<int32_t> part_begin, part_count;
     WaveItem* d_waves = nullptr;
@@ -59,8 +64,15 @@ struct ising_batch {
     size_t lds_bytes = 0;
     int32_t* d_ids_glb = nullptr;
     int32_t n_glb = 0;
-    int32_t n_tiled = 0;
-    bool off32 = true;  // every tiled lattice < 4 GiB
+    int32_t n_tiled = 0;  // lattices advanced by half-sweep launches
+    bool off32 = true;  // every such lattice < 4 GiB
+    // multi-sweep tiles
+    TileWork* d_tiles = nullptr;
+    int32_t n_tiles = 0;
+    Partial* d_tile_part = nullptr;  // kTileMaxSweeps x n_tiles
+    int32_t* d_ids_tile = nullptr;
+    int32_t n_tile_lat = 0;
+    std::vector<std::pair<Geometry, int32_t>> tile_shapes;  // distinct (geometry, tile width) of the tiles
     uint8_t* d_stage = nullptr;  // spin output staging, spin_stage_bytes of the largest L
     size_t stage_bytes = 0;
     std::map<std::pair<int32_t, int32_t>, hipGraphExec_t> graphs;  // (sweeps, every) -> executable
@@ -90,6 +102,9 @@ void release(ising_batch* b) {
     free_dev(b->d_ids_lds);
     free_dev(b->d_ids_glb);
     free_dev(b->d_stage);
+    free_dev(b->d_tiles);
+    free_dev(b->d_tile_part);
+    free_dev(b->d_ids_tile);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
     if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     if (b->join_ev) (void)hipEventDestroy(b->join_ev);
@@ -115,7 +130,28 @@ int check_plan(const ising_batch_plan& p) {
         return fail(ISING_EINVAL, "plan: words_per_thread must be 1, 2 or 4");
     if (!valid_block(p.tiled_block, 256)) return fail(ISING_EINVAL, "plan: tiled_block must be a multiple of 64 in [64, 256]");
     if (p.sweeps_per_graph < 1 || p.sweeps_per_graph > 100000) return fail(ISING_EINVAL, "plan: sweeps_per_graph must be in [1, 100000]");
+    if (p.tile_max_L < 0 || p.tile_max_L > kMaxL) return fail(ISING_EINVAL, "plan: tile_max_L must be in [0, %d]", kMaxL);
+    if (p.tile_max_L > 0) {
+        if (p.tile_sweeps < 1 || p.tile_sweeps > kTileMaxSweeps)
+            return fail(ISING_EINVAL, "plan: tile_sweeps must be in [1, %d]", kTileMaxSweeps);
+        if (p.tile_cols < 2 || p.tile_cols % 2) return fail(ISING_EINVAL, "plan: tile_cols must be even and >= 2");
+        if (!valid_block(p.tile_block, 1024)) return fail(ISING_EINVAL, "plan: tile_block must be a multiple of 64 in [64, 1024]");
+    }
     return ISING_OK;
+}
+
+// Interior width of lattice g's tiles under plan p (g.L: the whole lattice
+// in one workgroup), or 0 if its tiles do not fit in LDS.
+int32_t tile_width(const Geometry& g, const ising_batch_plan& p, size_t lds_limit) {
+    int32_t w = p.tile_cols >= g.L ? g.L : p.tile_cols;
+    if (w < g.L && w + 4 * p.tile_sweeps > g.L) w = g.L;  // the halos would overlap: whole lattice
+    return tile_lds_bytes(g.L, g.N, w, p.tile_sweeps) <= lds_limit ? w : 0;
+}
+
+size_t tile_launch_lds(const ising_batch* b, int32_t K) {
+    size_t m = 0;
+    for (const auto& gw : b->tile_shapes) m = std::max(m, tile_lds_bytes(gw.first.L, gw.first.N, gw.second, K));
+    return m;
 }
 
 // Upload the descriptors (pinned staging; the previous upload must have
@@ -162,8 +198,15 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     free_dev(b->d_partials);
     free_dev(b->d_ids_lds);
     free_dev(b->d_ids_glb);
+    free_dev(b->d_tiles);
+    free_dev(b->d_tile_part);
+    free_dev(b->d_ids_tile);
+    b->tile_shapes.clear();
     b->plan = p;
     const size_t lds_limit = resident_lds_limit(b->device);
+    const size_t tile_limit = tile_lds_limit(b->device);
+    std::vector<int32_t> ids_tile;
+    std::vector<TileWork> tiles;
     b->resident.assign(b->n, 0);
     b->units.assign(b->n, 0);
     b->part_begin.assign(b->n, 0);
@@ -185,6 +228,19 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
             }
             continue;
         }
+        const int32_t tw = g.L <= p.tile_max_L ? tile_width(g, p, tile_limit) : 0;
+        if (tw > 0) {
+            b->resident[i] = 3;
+            ids_tile.push_back(i);
+            b->part_begin[i] = (int32_t)tiles.size();
+            for (int32_t c0 = 0; c0 < g.L; c0 += tw)
+                tiles.push_back({i, c0, std::min(tw, g.L - c0), (int32_t)tiles.size()});
+            b->part_count[i] = (int32_t)tiles.size() - b->part_begin[i];
+            bool seen = false;
+            for (const auto& gw : b->tile_shapes) seen = seen || (gw.first.L == g.L && gw.second == tw);
+            if (!seen) b->tile_shapes.push_back({g, tw});
+            continue;
+        }
         const int64_t u = units_per_colour(g, p.words_per_thread);
         b->units[i] = u;
         b->off32 = b->off32 && fits_off32(g);
@@ -197,7 +253,9 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     b->n_waves = (int64_t)waves.size();
     b->n_lds = (int32_t)ids_lds.size();
     b->n_glb = (int32_t)ids_glb.size();
-    b->n_tiled = b->n - b->n_lds - b->n_glb;
+    b->n_tile_lat = (int32_t)ids_tile.size();
+    b->n_tiles = (int32_t)tiles.size();
+    b->n_tiled = b->n - b->n_lds - b->n_glb - b->n_tile_lat;
     b->lds_bytes = max_lds;
     if (!waves.empty()) {
         ISING_HIP(hipMalloc(&b->d_waves, sizeof(WaveItem) * waves.size()));
@@ -213,6 +271,14 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
         ISING_HIP(hipMalloc(&b->d_ids_glb, sizeof(int32_t) * ids_glb.size()));
         ISING_HIP(hipMemcpy(b->d_ids_glb, ids_glb.data(), sizeof(int32_t) * ids_glb.size(), hipMemcpyHostToDevice));
     }
+    if (!tiles.empty()) {
+        ISING_HIP(allow_tile_lds(b->device));
+        ISING_HIP(hipMalloc(&b->d_tiles, sizeof(TileWork) * tiles.size()));
+        ISING_HIP(hipMemcpy(b->d_tiles, tiles.data(), sizeof(TileWork) * tiles.size(), hipMemcpyHostToDevice));
+        ISING_HIP(hipMalloc(&b->d_tile_part, sizeof(Partial) * tiles.size() * kTileMaxSweeps));
+        ISING_HIP(hipMalloc(&b->d_ids_tile, sizeof(int32_t) * ids_tile.size()));
+        ISING_HIP(hipMemcpy(b->d_ids_tile, ids_tile.data(), sizeof(int32_t) * ids_tile.size(), hipMemcpyHostToDevice));
+    }
     return upload_descs(b, nullptr, nullptr, nullptr, 0);
 }
 
@@ -220,7 +286,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
 // (s + 1) % every == 0) on stream s0, resident work on stream s1.
 int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipStream_t s1) {
     const ising_batch_plan& p = b->plan;
-    const bool fork = (b->n_lds + b->n_glb) > 0 && b->n_tiled > 0 && s1 != nullptr;
+    const bool fork = (b->n_lds + b->n_glb + b->n_tile_lat) > 0 && b->n_tiled > 0 && s1 != nullptr;
     hipStream_t rs = fork ? s1 : s0;
     if (fork) {
         ISING_HIP(hipEventRecord(b->fork_ev, s0));
@@ -235,6 +301,27 @@ int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipS
     // A measured sweep s is finalized by the next launch on s0: the colour-0
     // half-sweep of sweep s + 1, or the chunk's end.
     auto measured = [&](int32_t s) { return every > 0 && s >= 0 && (s + 1) % every == 0; };
+    // tiles: up to tile_sweeps sweeps per launch, the launch's samples
+    // finalized right behind it on the same branch
+    for (int32_t done = 0; b->n_tile_lat && done < k;) {
+        const int32_t kb = std::min(p.tile_sweeps, k - done);
+        uint32_t mask = 0;
+        for (int32_t j = 0; j < kb; ++j)
+            if (measured(done + j)) mask |= 1u << j;
+        TileLaunch a = {};
+        a.tiles = b->d_tiles;
+        a.descs = b->d_desc;
+        a.states = b->d_state;
+        a.sweep_off = (uint32_t)done;
+        a.K = kb;
+        a.sample_mask = mask;
+        a.n_tiles = b->n_tiles;
+        a.partials = b->d_tile_part;
+        ISING_HIP(launch_tiles(a, b->n_tiles, p.tile_block, tile_launch_lds(b, kb), rs));
+        ISING_HIP(launch_finalize_tiles(b->d_desc, b->d_state, b->d_ids_tile, b->n_tile_lat, b->d_tile_part,
+                                        b->n_tiles, mask, (uint32_t)done, rs));
+        done += kb;
+    }
     if (b->n_tiled) {
         for (int32_t s = 0; s < k; ++s) {
             ISING_HIP(launch_halfsweep_multi(p.words_per_thread, p.tiled_block, b->d_desc, b->d_state, b->d_waves,
@@ -379,6 +466,10 @@ int create_impl(int32_t n, const int32_t* L, const uint64_t* seed, const int32_t
         p.words_per_thread = 1;
         p.tiled_block = 64;  // fastest measured for small and large batches alike
         p.sweeps_per_graph = 50;
+        p.tile_max_L = 0;
+        p.tile_sweeps = 2;
+        p.tile_cols = 16;
+        p.tile_block = 256;
     }
     int rc = apply_plan(b, p);
     if (rc != ISING_OK) {
@@ -393,7 +484,7 @@ std::string cache_key(const ising_batch* b) {
     std::map<int32_t, int32_t> hist;
     for (const auto& g : b->geo) hist[g.L] += 1;
     std::ostringstream os;
-    os << b->arch << "|";
+    os << b->arch << "|plan2|";
     bool first = true;
     for (auto& kv : hist) {
         os << (first ? "" : ",") << kv.first << "x" << kv.second;
@@ -414,9 +505,10 @@ bool cache_lookup(const char* path, const std::string& key, ising_batch_plan* p)
         ising_batch_plan q;
         if (std::sscanf(line.c_str() + at + want.size(),
                         " {\"resident_max_L\": %d, \"resident_block\": %d, \"words_per_thread\": %d, \"tiled_block\": %d, "
-                        "\"sweeps_per_graph\": %d",
-                        &q.resident_max_L, &q.resident_block, &q.words_per_thread, &q.tiled_block,
-                        &q.sweeps_per_graph) == 5) {
+                        "\"sweeps_per_graph\": %d, \"tile_max_L\": %d, \"tile_sweeps\": %d, \"tile_cols\": %d, "
+                        "\"tile_block\": %d",
+                        &q.resident_max_L, &q.resident_block, &q.words_per_thread, &q.tiled_block, &q.sweeps_per_graph,
+                        &q.tile_max_L, &q.tile_sweeps, &q.tile_cols, &q.tile_block) == 9) {
             *p = q;
             return true;
         }
@@ -440,9 +532,10 @@ void cache_store(const char* path, const std::string& key, const ising_batch_pla
     char buf[512];
     std::snprintf(buf, sizeof buf,
                   "\"%s\": {\"resident_max_L\": %d, \"resident_block\": %d, \"words_per_thread\": %d, \"tiled_block\": "
-                  "%d, \"sweeps_per_graph\": %d, \"ms_per_sweep\": %.6f}",
+                  "%d, \"sweeps_per_graph\": %d, \"tile_max_L\": %d, \"tile_sweeps\": %d, \"tile_cols\": %d, "
+                  "\"tile_block\": %d, \"ms_per_sweep\": %.6f}",
                   key.c_str(), p.resident_max_L, p.resident_block, p.words_per_thread, p.tiled_block, p.sweeps_per_graph,
-                  ms);
+                  p.tile_max_L, p.tile_sweeps, p.tile_cols, p.tile_block, ms);
     lines.push_back(buf);
     std::ofstream f(path, std::ios::trunc);
     f << "{\n";
@@ -651,11 +744,39 @@ int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path
             if (rc != ISING_OK) break;
             ising_batch_plan p = best;
             p.resident_max_L = 0;
+            p.tile_max_L = 0;
             p.words_per_thread = wpt;
             p.tiled_block = blk;
             p.sweeps_per_graph = std::min(sweeps, 20);
             rc = consider(p);
         }
+    // 1b) multi-sweep tiles for every lattice (sweeps per launch, tile
+    // width, workgroup size), then the largest L that stays on tiles
+    const int32_t max_L = distinct.back();
+    const ising_batch_plan half_best = best;
+    for (int K : {1, 2, 4})
+        for (int cols : {16, 32, 64})
+            for (int blk : {256, 512}) {
+                if (rc != ISING_OK) break;
+                ising_batch_plan p = half_best;
+                p.resident_max_L = 0;
+                p.tile_max_L = max_L;
+                p.tile_sweeps = K;
+                p.tile_cols = cols;
+                p.tile_block = blk;
+                p.sweeps_per_graph = std::max(K, (std::min(sweeps, 20) / K) * K);
+                rc = consider(p);
+            }
+    {
+        const ising_batch_plan tile_best = best;
+        if (tile_best.tile_max_L > 0)
+            for (int32_t Lt : distinct) {
+                if (rc != ISING_OK || Lt >= max_L) break;
+                ising_batch_plan p = tile_best;
+                p.tile_max_L = Lt;
+                rc = consider(p);
+            }
+    }
     // 2) which sizes go resident, and the resident workgroup size: only sizes
     // whose lattice fits one workgroup's LDS are tried
     const ising_batch_plan tiled_best = best;
@@ -687,9 +808,7 @@ int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path
                              return x.first < y.first;
                          });
         auto same = [](const ising_batch_plan& x, const ising_batch_plan& y) {
-            return x.resident_max_L == y.resident_max_L && x.resident_block == y.resident_block &&
-                   x.words_per_thread == y.words_per_thread && x.tiled_block == y.tiled_block &&
-                   x.sweeps_per_graph == y.sweeps_per_graph;
+            return std::memcmp(&x, &y, sizeof x) == 0;
         };
         std::vector<ising_batch_plan> top;
         for (const auto& c : seen) {

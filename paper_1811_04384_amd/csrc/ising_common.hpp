@@ -96,10 +96,87 @@ struct WaveItem {
     int32_t seg0;  // segment handled by lane 0
 };
 
-// Partial sums of one wavefront: antiparallel bonds and up spins.
+// Partial sums of one wavefront (or tile): antiparallel bonds and up spins.
 struct Partial {
     uint32_t anti;
     uint32_t ups;
+};
+
+// One LDS tile of a multi-sweep launch: every word row of the interior word
+// columns [c0, c0 + w) of a lattice (w >= L: the whole lattice).
+struct TileWork {
+    int32_t lattice;  // index into the launch's descriptors
+    int32_t c0;       // first interior column
+    int32_t w;        // interior columns (even)
+    int32_t part;     // this tile's slot in the partial sums of a sample
+};
+
+// Largest number of sweeps of one multi-sweep launch.
+constexpr int kTileMaxSweeps = 16;
+
+// A multi-sweep launch over a table of tiles.  With `states` the sweep index
+// of lattice i is states[i].t + sweep_off and its thresholds and sweep limit
+// come from descs[i]; without, every tile uses t0, the key (k0, k1) and
+// t4, t8 of the launch, and only the geometry and words of descs.  Sample j of the
+// launch (bit j of sample_mask: after its j-th sweep) goes to
+// partials[ordinal * n_tiles + tile.part], ordinal = the number of samples
+// before it in this launch.
+struct TileLaunch {
+    const TileWork* tiles;
+    const LatticeDesc* descs;
+    LatticeState* states;
+    uint64_t t0;
+    uint32_t k0, k1;  // key (without states)
+    uint32_t t4, t8;
+    uint32_t sweep_off;
+    int32_t K;
+    uint32_t sample_mask;
+    int32_t n_tiles;
+    Partial* partials;
+};
+
+}  // namespace ising
+
+namespace ising {
+
+// One resident tile: every word row of the interior word columns
+// [c0, c0 + w) of a lattice (w >= L: the whole lattice), and the tiles that
+// own the columns beside it (their indices in the launch).
+struct PersistTile {
+    int32_t lattice;
+    int32_t c0, w;
+    int32_t left, right;
+    int32_t part;  // slot in the partial sums of a sample
+};
+
+// A launch of resident tiles: K sweeps of every listed tile.  The sweep
+// index, key and thresholds come from states/descs or from the launch as for
+// TileLaunch.  Sample after sweep j of the launch iff (sample_base + j + 1)
+// is a multiple of every (every = 0: none); the sample's partial sums go to
+// partials[ordinal * n_tiles + tile.part].  exch holds exch_tile_words
+// (>= 4 N) words per tile, flags one word per tile; both persist between
+// launches.  A tile's flag reaches 2 t + s + 1 when it has published its
+// boundary words of half-sweep s (0 or 1) of its lattice's absolute sweep
+// t, so flags only grow while sweep counters do (a counter set back needs
+// its lattice's flags zeroed).  A wait longer than wait_ticks (100 MHz
+// clock) sets *error and ends the launch early.
+struct PersistLaunch {
+    const PersistTile* tiles;
+    const LatticeDesc* descs;
+    LatticeState* states;
+    uint64_t t0;
+    uint32_t k0, k1, t4, t8;
+    uint32_t sweep_off;
+    int32_t K;
+    int32_t every;
+    int64_t sample_base;
+    int32_t n_tiles;
+    Partial* partials;
+    uint64_t* exch;
+    int64_t exch_tile_words;
+    uint64_t* flags;
+    uint32_t* error;
+    uint64_t wait_ticks;
 };
 
 }  // namespace ising

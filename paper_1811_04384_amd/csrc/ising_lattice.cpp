@@ -31,10 +31,30 @@ struct ising_lattice {
     uint64_t* strip_codes = nullptr;  // their acceptance codes
     uint8_t* d_stage = nullptr;       // spin input/output staging, spin_stage_bytes(L)
     Moments* d_scan = nullptr;        // moment sums of up to kScanBlock temperatures of a scan
+    // multi-sweep LDS tiles (tile_k = 0: one launch per half-sweep)
+    int tile_k = 0, tile_cols = 0, tile_block = 256;
+    int32_t n_tiles = 0;
+    TileWork* d_tiles = nullptr;
+    LatticeDesc* d_desc = nullptr;  // words and geometry of this lattice for the tile kernel
+    Partial* d_tpart = nullptr;     // kTileMaxSweeps x n_tiles partial sums
+    // resident tiles with boundary exchange (res_cols = 0: off)
+    int res_cols = 0, res_block = 256, res_sweeps = 0;
+    int32_t n_res = 0;
+    size_t res_lds = 0;
+    PersistTile* d_res = nullptr;
+    uint64_t* d_exch = nullptr;
+    uint64_t* d_flags = nullptr;
+    uint32_t* d_err = nullptr;
+    uint32_t* h_err = nullptr;      // pinned copy of d_err, refreshed after every launch
+    Partial* d_rpart = nullptr;     // res_sweeps x n_res partial sums
+    int64_t* d_rEM = nullptr;       // 2 x res_sweeps sample scratch (moments without a series)
 };
 
 // Temperatures of a scan whose moment sums are read back together.
 constexpr int32_t kScanBlock = 256;
+
+static int ensure_desc(ising_lattice* h);
+static void free_resident(ising_lattice* h);
 
 namespace ising {
 std::string& last_error_ref() {
@@ -112,6 +132,16 @@ static void release(ising_lattice* h) {
     if (h->strip_codes) (void)hipFree(h->strip_codes);
     if (h->d_stage) (void)hipFree(h->d_stage);
     if (h->d_scan) (void)hipFree(h->d_scan);
+    if (h->d_tiles) (void)hipFree(h->d_tiles);
+    if (h->d_desc) (void)hipFree(h->d_desc);
+    if (h->d_tpart) (void)hipFree(h->d_tpart);
+    if (h->d_res) (void)hipFree(h->d_res);
+    if (h->d_exch) (void)hipFree(h->d_exch);
+    if (h->d_flags) (void)hipFree(h->d_flags);
+    if (h->d_err) (void)hipFree(h->d_err);
+    if (h->h_err) (void)hipHostFree(h->h_err);
+    if (h->d_rpart) (void)hipFree(h->d_rpart);
+    if (h->d_rEM) (void)hipFree(h->d_rEM);
     delete h;
 }
 
@@ -187,9 +217,17 @@ int ising_create_in(int32_t L, uint64_t seed, int32_t init, void* dev_words, siz
     return create_impl(L, seed, init, dev_words, bytes, stream, out);
 }
 
+// Resident-tile flags follow the sweep counter: zero them when it goes back.
+static int counter_set_back(ising_lattice* h) {
+    if (h->d_flags) ISING_HIP(hipMemsetAsync(h->d_flags, 0, sizeof(uint64_t) * h->n_res, h->stream));
+    return ISING_OK;
+}
+
 int ising_reset(ising_lattice* h, uint64_t seed, int32_t init) {
     if (!h) return fail(ISING_EINVAL, "ising_reset: null handle");
     if (init != ISING_COLD && init != ISING_HOT) return fail(ISING_EINVAL, "ising_reset: init must be 0 or 1");
+    const int rc = counter_set_back(h);
+    if (rc != ISING_OK) return rc;
     h->seed = seed;
     h->t = 0;
     ISING_HIP(launch_init(h->W, h->g, seed, init, h->stream));
@@ -219,10 +257,105 @@ static SweepArgs sweep_args(const ising_lattice* h, uint64_t t, uint32_t t4, uin
     return a;
 }
 
+// Enqueue n sweeps in multi-sweep tile launches of up to h->tile_k sweeps
+// (the handle's words), starting at absolute sweep t0; the samples a launch
+// takes are finalized right after it, in order.
+static int enqueue_tile_sweeps(const ising_lattice* h, uint64_t t0, double T, int64_t n, int32_t every, int64_t* dev_E,
+                               int64_t* dev_M, Moments* mom) {
+    TileLaunch a = {};
+    a.tiles = h->d_tiles;
+    a.descs = h->d_desc;
+    a.states = nullptr;
+    a.k0 = (uint32_t)h->seed;
+    a.k1 = (uint32_t)(h->seed >> 32);
+    thresholds_of(T, &a.t4, &a.t8);
+    a.sweep_off = 0;
+    a.n_tiles = h->n_tiles;
+    a.partials = h->d_tpart;
+    for (int64_t done = 0; done < n;) {
+        const int32_t kb = (int32_t)std::min<int64_t>(h->tile_k, n - done);
+        uint32_t mask = 0;
+        int32_t n_samples = 0;
+        int64_t first = -1;
+        for (int32_t j = 0; j < kb; ++j) {
+            if (every > 0 && (done + j + 1) % every == 0) {
+                mask |= 1u << j;
+                if (first < 0) first = (done + j + 1) / every - 1;
+                n_samples += 1;
+            }
+        }
+        a.t0 = t0 + (uint64_t)done;
+        a.K = kb;
+        a.sample_mask = mask;
+        ISING_HIP(launch_tiles(a, h->n_tiles, h->tile_block, tile_lds_bytes(h->g.L, h->g.N, h->tile_cols, kb),
+                               h->stream));
+        if (n_samples)
+            ISING_HIP(launch_finalize_samples(h->d_tpart, h->n_tiles, n_samples, h->g.L, dev_E, dev_M, first, mom,
+                                              nullptr, h->stream));
+        done += kb;
+    }
+    return ISING_OK;
+}
+
+// A wait of resident tiles longer than this (100 MHz clock ticks: one
+// second) abandons the launch.
+constexpr uint64_t kResidentWaitTicks = 100000000ull;
+
+// Error left by an earlier resident-tile launch (its copy lands in pinned
+// memory behind the launch); cleared once reported.
+static int resident_error(const ising_lattice* h) {
+    if (h->h_err && *(volatile uint32_t*)h->h_err) {
+        *(volatile uint32_t*)h->h_err = 0;
+        return fail(ISING_EHIP, "resident tiles: a launch waited too long for its neighbour tiles and was abandoned; "
+                                "the lattice state is undefined");
+    }
+    return ISING_OK;
+}
+
+// Enqueue n sweeps as launches of resident tiles of up to h->res_sweeps
+// sweeps each; each launch's samples are reduced right behind it.
+static int enqueue_resident_sweeps(ising_lattice* h, uint64_t t0, double T, int64_t n, int32_t every, int64_t* dev_E,
+                                   int64_t* dev_M, Moments* mom) {
+    PersistLaunch a = {};
+    a.tiles = h->d_res;
+    a.descs = h->d_desc;
+    a.k0 = (uint32_t)h->seed;
+    a.k1 = (uint32_t)(h->seed >> 32);
+    thresholds_of(T, &a.t4, &a.t8);
+    a.every = every;
+    a.n_tiles = h->n_res;
+    a.partials = h->d_rpart;
+    a.exch = h->d_exch;
+    a.exch_tile_words = 4 * (int64_t)h->g.N;
+    a.flags = h->d_flags;
+    a.error = h->d_err;
+    a.wait_ticks = kResidentWaitTicks;
+    for (int64_t done = 0; done < n;) {
+        const int32_t kb = (int32_t)std::min<int64_t>(h->res_sweeps, n - done);
+        a.t0 = t0 + (uint64_t)done;
+        a.K = kb;
+        a.sample_base = done;
+        ISING_HIP(launch_persist(a, h->n_res, h->res_block, h->res_lds, h->stream));
+        const int64_t n_samples = every > 0 ? (done + kb) / every - done / every : 0;
+        if (n_samples > 0) {
+            const int64_t idx0 = done / every;  // series index of the launch's first sample
+            int64_t* E = dev_E ? dev_E + idx0 : h->d_rEM;
+            int64_t* M = dev_M ? dev_M + idx0 : h->d_rEM + h->res_sweeps;
+            ISING_HIP(launch_samples(h->d_rpart, h->n_res, (int32_t)n_samples, h->g.L, E, M, mom, h->stream));
+        }
+        ISING_HIP(hipMemcpyAsync(h->h_err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+        done += kb;
+    }
+    return ISING_OK;
+}
+
 // Enqueue n sweeps of lattice words W (the handle's or a scratch copy)
 // starting at absolute sweep t0.
 static int enqueue_sweeps(const ising_lattice* h, uint64_t* W, uint64_t t0, double T, int64_t n, int32_t every,
                           int64_t* dev_E, int64_t* dev_M, Moments* mom, int wpt, int block) {
+    if (h->res_cols > 0 && W == h->W)
+        return enqueue_resident_sweeps(const_cast<ising_lattice*>(h), t0, T, n, every, dev_E, dev_M, mom);
+    if (h->tile_k > 0 && W == h->W) return enqueue_tile_sweeps(h, t0, T, n, every, dev_E, dev_M, mom);
     uint32_t t4, t8;
     thresholds_of(T, &t4, &t8);
     for (int64_t k = 1; k <= n; ++k) {
@@ -243,7 +376,9 @@ static int sweep_impl(ising_lattice* h, double T, int64_t n, int32_t every, int6
     if (!h) return fail(ISING_EINVAL, "ising_sweep: null handle");
     if (!valid_T(T)) return fail(ISING_EINVAL, "ising_sweep: T must be finite and > 0 (got %g)", T);
     if (n < 0) return fail(ISING_EINVAL, "ising_sweep: n_sweeps must be >= 0");
-    int rc = enqueue_sweeps(h, h->W, h->t, T, n, every, dev_E, dev_M, mom, h->wpt, h->block);
+    int rc = resident_error(h);
+    if (rc != ISING_OK) return rc;
+    rc = enqueue_sweeps(h, h->W, h->t, T, n, every, dev_E, dev_M, mom, h->wpt, h->block);
     if (rc != ISING_OK) return rc;
     h->t += (uint64_t)n;
     return ISING_OK;
@@ -408,6 +543,8 @@ int ising_observables(ising_lattice* h, int64_t* E, int64_t* M) {
     int64_t em[2];
     ISING_HIP(hipMemcpyAsync(em, h->d_EM, sizeof em, hipMemcpyDeviceToHost, h->stream));
     ISING_HIP(hipStreamSynchronize(h->stream));
+    int rc = resident_error(h);
+    if (rc != ISING_OK) return rc;
     *E = em[0];
     *M = em[1];
     return ISING_OK;
@@ -440,6 +577,10 @@ int ising_get_sweep_count(ising_lattice* h, uint64_t* t) {
 
 int ising_set_sweep_count(ising_lattice* h, uint64_t t) {
     if (!h) return fail(ISING_EINVAL, "ising_set_sweep_count: null handle");
+    if (t < h->t) {
+        const int rc = counter_set_back(h);
+        if (rc != ISING_OK) return rc;
+    }
     h->t = t;
     return ISING_OK;
 }
@@ -467,10 +608,176 @@ int ising_get_plan(ising_lattice* h, int32_t* wpt, int32_t* block) {
     return ISING_OK;
 }
 
+int ising_set_tiling(ising_lattice* h, int32_t sweeps_per_launch, int32_t tile_cols, int32_t block) {
+    if (!h) return fail(ISING_EINVAL, "ising_set_tiling: null handle");
+    const int32_t L = h->g.L, N = h->g.N, K = sweeps_per_launch;
+    if (K == 0) {
+        h->tile_k = 0;
+        return ISING_OK;
+    }
+    if (K < 0 || K > kTileMaxSweeps)
+        return fail(ISING_EINVAL, "ising_set_tiling: sweeps_per_launch must be in [0, %d]", kTileMaxSweeps);
+    if (tile_cols < 2 || tile_cols % 2) return fail(ISING_EINVAL, "ising_set_tiling: tile_cols must be even and >= 2");
+    if (!valid_block(block, 1024)) return fail(ISING_EINVAL, "ising_set_tiling: block must be a multiple of 64 in [64, 1024]");
+    const bool whole = tile_cols >= L;
+    if (!whole && tile_cols + 4 * K > L)
+        return fail(ISING_EINVAL, "ising_set_tiling: a tile of %d columns with halos of %d exceeds L = %d (use tile_cols >= L)",
+                    tile_cols, 2 * K, L);
+    const size_t need = tile_lds_bytes(L, N, whole ? L : tile_cols, K);
+    const size_t have = tile_lds_limit(h->device);
+    if (need > have)
+        return fail(ISING_EINVAL, "ising_set_tiling: a tile needs %zu bytes of LDS, %zu available", need, have);
+    std::vector<TileWork> tiles;
+    const int32_t w = whole ? L : tile_cols;
+    for (int32_t c0 = 0; c0 < L; c0 += w) tiles.push_back({0, c0, std::min(w, L - c0), (int32_t)tiles.size()});
+    ISING_HIP(hipStreamSynchronize(h->stream));  // earlier launches may still read the old tables
+    if (h->d_tiles) (void)hipFree(h->d_tiles);
+    if (h->d_tpart) (void)hipFree(h->d_tpart);
+    h->d_tiles = nullptr;
+    h->d_tpart = nullptr;
+    h->tile_k = 0;
+    ISING_HIP(allow_tile_lds(h->device));
+    free_resident(h);  // resident tiles off
+    const int rc = ensure_desc(h);
+    if (rc != ISING_OK) return rc;
+    ISING_HIP(hipMalloc(&h->d_tiles, sizeof(TileWork) * tiles.size()));
+    ISING_HIP(hipMemcpy(h->d_tiles, tiles.data(), sizeof(TileWork) * tiles.size(), hipMemcpyHostToDevice));
+    ISING_HIP(hipMalloc(&h->d_tpart, sizeof(Partial) * tiles.size() * kTileMaxSweeps));
+    h->n_tiles = (int32_t)tiles.size();
+    h->tile_k = K;
+    h->tile_cols = w;
+    h->tile_block = block;
+    return ISING_OK;
+}
+
+static int ensure_desc(ising_lattice* h) {
+    if (h->d_desc) return ISING_OK;
+    LatticeDesc d = {};
+    d.W = h->W;
+    d.L = h->g.L;
+    d.N = h->g.N;
+    d.istar = h->g.istar;
+    d.sh_star = h->g.sh_star;
+    d.sweep_limit = 0x7FFFFFFF;
+    ISING_HIP(hipMalloc(&h->d_desc, sizeof(LatticeDesc)));
+    ISING_HIP(hipMemcpy(h->d_desc, &d, sizeof d, hipMemcpyHostToDevice));
+    return ISING_OK;
+}
+
+static void free_resident(ising_lattice* h) {
+    if (h->d_res) (void)hipFree(h->d_res);
+    if (h->d_exch) (void)hipFree(h->d_exch);
+    if (h->d_flags) (void)hipFree(h->d_flags);
+    if (h->d_rpart) (void)hipFree(h->d_rpart);
+    if (h->d_rEM) (void)hipFree(h->d_rEM);
+    h->d_res = nullptr;
+    h->d_exch = nullptr;
+    h->d_flags = nullptr;
+    h->d_rpart = nullptr;
+    h->d_rEM = nullptr;
+    h->res_cols = 0;
+    h->n_res = 0;
+}
+
+// The resident tiles of one lattice (interior width w, the last one
+// narrower), indexed by workgroup: consecutive workgroups are dealt to the
+// 8 XCDs in turn, so when the tile count is a multiple of 8 tile t goes to
+// workgroup 8 (t mod m) + t div m (m = count / 8) and every XCD holds a run
+// of neighbouring tiles, which then trade their boundary words inside one
+// XCD except at the ends of the runs.  part_base offsets the partial slots.
+static std::vector<PersistTile> resident_tile_table(int32_t lattice, int32_t L, int32_t w, int32_t part_base) {
+    int32_t n = 0;
+    for (int32_t c0 = 0; c0 < L; c0 += w) ++n;
+    const bool spread = n % 8 == 0;
+    const int32_t m = n / 8;
+    auto block_of = [&](int32_t t) { return spread ? 8 * (t % m) + t / m : t; };
+    std::vector<PersistTile> tiles(n);
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t c0 = t * w;
+        tiles[block_of(t)] = {lattice, c0, std::min(w, L - c0), block_of((t + n - 1) % n), block_of((t + 1) % n),
+                              part_base + t};
+    }
+    return tiles;
+}
+
+// Largest number of sweeps of one resident-tile launch.
+constexpr int32_t kResidentMaxSweeps = 4096;
+
+int ising_set_resident_tiles(ising_lattice* h, int32_t tile_cols, int32_t block, int32_t max_sweeps) {
+    if (!h) return fail(ISING_EINVAL, "ising_set_resident_tiles: null handle");
+    ISING_HIP(hipStreamSynchronize(h->stream));  // earlier launches may still read the old tables
+    int rc = resident_error(h);
+    if (rc != ISING_OK) return rc;
+    if (tile_cols == 0) {
+        free_resident(h);
+        return ISING_OK;
+    }
+    const int32_t L = h->g.L, N = h->g.N;
+    if (tile_cols < 2 || tile_cols % 2) return fail(ISING_EINVAL, "ising_set_resident_tiles: tile_cols must be even and >= 2");
+    if (!valid_block(block, 1024))
+        return fail(ISING_EINVAL, "ising_set_resident_tiles: block must be a multiple of 64 in [64, 1024]");
+    if (max_sweeps < 1 || max_sweeps > kResidentMaxSweeps)
+        return fail(ISING_EINVAL, "ising_set_resident_tiles: max_sweeps must be in [1, %d]", kResidentMaxSweeps);
+    const int32_t w = tile_cols >= L ? L : tile_cols;
+    const size_t lds = persist_lds_bytes(L, N, w);
+    if (lds > persist_lds_limit(h->device))
+        return fail(ISING_EINVAL, "ising_set_resident_tiles: a tile needs %zu bytes of LDS, %zu available", lds,
+                    persist_lds_limit(h->device));
+    ISING_HIP(allow_persist_lds(h->device));
+    std::vector<PersistTile> tiles = resident_tile_table(0, L, w, 0);
+    const int32_t n = (int32_t)tiles.size();
+    int64_t capacity = 0;
+    ISING_HIP(persist_capacity(block, lds, h->device, &capacity));
+    if (n > capacity)
+        return fail(ISING_EINVAL, "ising_set_resident_tiles: %d tiles of %d threads and %zu bytes of LDS exceed the %lld "
+                    "the device holds at once", n, block, lds, (long long)capacity);
+    free_resident(h);
+    h->tile_k = 0;  // multi-sweep halo tiles off
+    rc = ensure_desc(h);
+    if (rc != ISING_OK) return rc;
+    hipError_t e = hipMalloc(&h->d_res, sizeof(PersistTile) * n);
+    if (e == hipSuccess) e = hipMemcpy(h->d_res, tiles.data(), sizeof(PersistTile) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&h->d_exch, sizeof(uint64_t) * 4 * (size_t)N * n);
+    if (e == hipSuccess) e = hipMalloc(&h->d_flags, sizeof(uint64_t) * n);
+    if (e == hipSuccess) e = hipMemset(h->d_flags, 0, sizeof(uint64_t) * n);
+    if (e == hipSuccess && !h->d_err) e = hipMalloc(&h->d_err, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(h->d_err, 0, sizeof(uint32_t));
+    if (e == hipSuccess && !h->h_err) e = hipHostMalloc(&h->h_err, sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&h->d_rpart, sizeof(Partial) * (size_t)max_sweeps * n);
+    if (e == hipSuccess) e = hipMalloc(&h->d_rEM, sizeof(int64_t) * 2 * (size_t)max_sweeps);
+    if (e != hipSuccess) {
+        free_resident(h);
+        return hip_fail(e, "ising_set_resident_tiles");
+    }
+    *h->h_err = 0;
+    h->n_res = n;
+    h->res_cols = w;
+    h->res_block = block;
+    h->res_sweeps = max_sweeps;
+    h->res_lds = lds;
+    return ISING_OK;
+}
+
+int ising_get_resident_tiles(ising_lattice* h, int32_t* tile_cols, int32_t* block, int32_t* max_sweeps) {
+    if (!h || !tile_cols || !block || !max_sweeps) return fail(ISING_EINVAL, "ising_get_resident_tiles: null argument");
+    *tile_cols = h->res_cols;
+    *block = h->res_cols ? h->res_block : 0;
+    *max_sweeps = h->res_cols ? h->res_sweeps : 0;
+    return ISING_OK;
+}
+
+int ising_get_tiling(ising_lattice* h, int32_t* sweeps_per_launch, int32_t* tile_cols, int32_t* block) {
+    if (!h || !sweeps_per_launch || !tile_cols || !block) return fail(ISING_EINVAL, "ising_get_tiling: null argument");
+    *sweeps_per_launch = h->tile_k;
+    *tile_cols = h->tile_k ? h->tile_cols : 0;
+    *block = h->tile_k ? h->tile_block : 0;
+    return ISING_OK;
+}
+
 int ising_synchronize(ising_lattice* h) {
     if (!h) return fail(ISING_EINVAL, "ising_synchronize: null handle");
     ISING_HIP(hipStreamSynchronize(h->stream));
-    return ISING_OK;
+    return resident_error(h);
 }
 
 int ising_autotune(ising_lattice* h, double T, double* best_ms_per_sweep) {

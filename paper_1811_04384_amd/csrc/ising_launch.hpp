@@ -108,6 +108,47 @@ hipError_t launch_observe_multi(const LatticeDesc* descs, LatticeState* states, 
 hipError_t launch_reset_sums(LatticeState* states, int32_t n_lat, hipStream_t s);
 hipError_t launch_begin_call(LatticeState* states, int32_t n_lat, hipStream_t s);
 
+// ---- multi-sweep LDS tiles --------------------------------------------------
+
+// Dynamic LDS of one tile of interior width w (w >= L: the whole lattice)
+// for a launch of K sweeps.  A tile fits if its bytes are at most
+// tile_lds_limit(device); allow_tile_lds(device) must have run once before
+// the first launch_tiles (outside any graph capture).
+size_t tile_lds_bytes(int32_t L, int32_t N, int32_t w, int32_t K);
+size_t tile_lds_limit(int device);
+hipError_t allow_tile_lds(int device);
+hipError_t launch_tiles(const TileLaunch& a, int32_t n_tiles_launched, int block, size_t lds_bytes, hipStream_t s);
+// E, M of n_samples samples of one lattice from its tiles' partials, in
+// order: series entries idx0 .. idx0 + n_samples - 1, moment sums, and the
+// last sample into out_EM[0..1] (each optional).
+hipError_t launch_finalize_samples(const Partial* partials, int32_t n_tiles, int32_t n_samples, int32_t L,
+                                   int64_t* series_E, int64_t* series_M, int64_t idx0, Moments* mom, int64_t* out_EM,
+                                   hipStream_t s);
+
+// The samples of one tile launch (sample_mask, first sweep sweep_off of the
+// chunk) for the listed lattices of a batch: series entries, moment sums,
+// last E and M, in order.
+hipError_t launch_finalize_tiles(const LatticeDesc* descs, LatticeState* states, const int32_t* ids, int32_t n_lat,
+                                 const Partial* partials, int32_t n_tiles, uint32_t sample_mask, uint32_t sweep_off,
+                                 hipStream_t s);
+
+// ---- resident LDS tiles with boundary exchange -------------------------------
+
+// Dynamic LDS of one resident tile of interior width w (w >= L: the whole
+// lattice); the limit and the one-time attribute as for the tiles above.
+size_t persist_lds_bytes(int32_t L, int32_t N, int32_t w);
+size_t persist_lds_limit(int device);
+hipError_t allow_persist_lds(int device);
+// How many resident tiles of `block` threads and lds_bytes of LDS the device
+// holds at once (a launch must not exceed it).
+hipError_t persist_capacity(int block, size_t lds_bytes, int device, int64_t* tiles);
+hipError_t launch_persist(const PersistLaunch& a, int32_t n_tiles, int block, size_t lds_bytes, hipStream_t s);
+// E, M of n_samples samples of one lattice from its tiles' partials
+// (sample k in partials[k n_tiles ...]) into out_E[k], out_M[k], then, with
+// mom, added to the moment sums in order.
+hipError_t launch_samples(const Partial* partials, int32_t n_tiles, int32_t n_samples, int32_t L, int64_t* out_E,
+                          int64_t* out_M, Moments* mom, hipStream_t s);
+
 // Largest dynamic LDS a resident workgroup may use on this device.
 size_t resident_lds_limit(int device);
 

@@ -1,0 +1,126 @@
+// The update of one word held in LDS, shared by the kernels that keep a
+// band of word columns (every word row of them) in LDS: the multi-sweep
+// tiles with redundant halos and the resident tiles that exchange their
+// boundary columns.  Lanes of a wavefront may hold words of different rows,
+// so the row-dependent parts (live slots, the wrap between the first and
+// last word rows, the row-(L-1) patch) are selects, not branches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ising_device.hpp"
+
+namespace ising {
+
+// q = n div d, r = n mod d for 0 <= n < 2^24, 1 <= d < 2^16, from a float
+// estimate (relative error below 2^-22, so off by at most one) and one
+// correction, without branches.
+__device__ __forceinline__ void divmod_small(int n, int d, float rcp, int& q, int& r) {
+    q = (int)((float)n * rcp);
+    r = n - q * d;
+    const int lo = r < 0 ? 1 : 0, hi = r >= d ? 1 : 0;
+    q += hi - lo;
+    r += (lo - hi) * d;
+}
+
+// What every word update of one lattice in one half-sweep shares
+// (wave-uniform).
+struct LdsSweep {
+    int L, N, istar, sh_star, pstar;  // pstar = (L - 1) div N
+    uint32_t t_lo, t_hi, k0, k1, t4, t8;
+    bool all_blocks;                  // every row has more than 16 live positions
+};
+
+// Neighbourhood words of (I, x) read from LDS: T is the band [N][width],
+// xl / xr the local columns of the left / right neighbours.
+__device__ __forceinline__ Nbhd lds_nbhd(const uint64_t* __restrict__ T, int width, int N, int istar, int I, int x,
+                                         int xl, int xr) {
+    Nbhd nb;
+    const int row = I * width;
+    nb.w = T[row + x];
+    nb.lf = T[row + xl];
+    nb.rt = T[row + xr];
+    nb.up = T[(I > 0 ? I - 1 : N - 1) * width + x];
+    nb.dn = T[(I < N - 1 ? I + 1 : 0) * width + x];
+    // the patch word (row I* for I = 0, row 0 for I = I*); other rows read
+    // row 0 and ignore it
+    nb.patch = T[(I == 0 ? istar : 0) * width + x];
+    return nb;
+}
+
+// Vertical neighbours with the wrap of Section 3 (Fig. 2) and the row-(L-1)
+// patch, as fix_up / fix_down, written as selects on the lane's row.
+__device__ __forceinline__ uint64_t up_of(const Nbhd& n, int I, int sh_star) {
+    const uint64_t wrapped = (n.up >> 3) | (((n.patch >> sh_star) & 1ull) << 60);
+    return I > 0 ? n.up : wrapped;
+}
+__device__ __forceinline__ uint64_t down_of(const Nbhd& n, int I, int N, int istar, int sh_star) {
+    const uint64_t d = I < N - 1 ? n.dn : ((n.dn << 3) & kLow63);
+    const uint64_t patched = (d & ~(1ull << sh_star)) | (((n.patch >> 60) & 1ull) << sh_star);
+    return I == istar ? patched : d;
+}
+
+// New value of the word (I, J) from its neighbourhood: the 21 acceptance
+// codes from Philox blocks g = 0..4 of counter (t, I L + J) and the
+// position-20 uniform u20 (drawn from the shared block 5 of the word's
+// 8-column group), then the bit-sliced flip of Table 1 and the Metropolis
+// rule.  With meas (wave-uniform), adds the word's antiparallel bonds and its
+// and its left neighbour's up spins when count (per lane) is set.
+__device__ __forceinline__ uint64_t lds_word_update(const LdsSweep& s, const RoundKeys& rk, const Nbhd& nb, int I,
+                                                    int J, uint32_t u20, bool meas, bool count, uint32_t& anti,
+                                                    uint32_t& ups) {
+    const int n_live = s.pstar + (I <= s.istar ? 1 : 0);
+    const uint64_t live = kSpinBits & (~0ull << (3 * (21 - n_live)));
+    const uint32_t c1 = (uint32_t)I * (uint32_t)s.L + (uint32_t)J;
+    Codes codes = {0u, 0u, 0u};
+    if (s.all_blocks) {
+#pragma unroll
+        for (int g = 0; g < 5; ++g) {
+            const U4 r = philox_lane_c1(s.t_lo, c1, s.t_hi, (uint32_t)g | (1u << 3), s.k0, s.k1, rk);
+            append_draw(codes, 4 * g + 0, r.x, s.t4, s.t8);
+            append_draw(codes, 4 * g + 1, r.y, s.t4, s.t8);
+            append_draw(codes, 4 * g + 2, r.z, s.t4, s.t8);
+            append_draw(codes, 4 * g + 3, r.w, s.t4, s.t8);
+        }
+    } else {  // small lattices: blocks past the last live position are skipped
+#pragma unroll
+        for (int g = 0; g < 5; ++g) {
+            if (4 * g < n_live) {
+                const U4 r = philox_lane_c1(s.t_lo, c1, s.t_hi, (uint32_t)g | (1u << 3), s.k0, s.k1, rk);
+                append_draw(codes, 4 * g + 0, r.x, s.t4, s.t8);
+                append_draw(codes, 4 * g + 1, r.y, s.t4, s.t8);
+                append_draw(codes, 4 * g + 2, r.z, s.t4, s.t8);
+                append_draw(codes, 4 * g + 3, r.w, s.t4, s.t8);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) append_code(codes, 4 * g + k, 0u);
+            }
+        }
+    }
+    append_draw(codes, 20, u20, s.t4, s.t8);  // a dead slot when n_live < 21 (masked by live)
+    const uint64_t up = up_of(nb, I, s.sh_star);
+    const uint64_t dn = down_of(nb, I, s.N, s.istar, s.sh_star);
+    const uint64_t nw = nb.w ^ flip_mask(nb.w, up, dn, nb.lf, nb.rt, assemble_codes(codes), live);
+    if (meas) {
+        uint32_t a = 0, u = 0;
+        measure_word(nw, up, dn, nb.lf, nb.rt, live, a, u);
+        anti += count ? a : 0u;
+        ups += count ? u : 0u;
+    }
+    return nw;
+}
+
+__device__ __forceinline__ uint32_t pick4(const uint4& v, uint32_t q) {
+    return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
+}
+
+// Philox block 5 of word row I, 8-column group grp and colour c at sweep t:
+// the position-20 uniforms of the group's four words of that colour.
+__device__ __forceinline__ uint4 block5(const LdsSweep& s, const RoundKeys& rk, int I, int grp, int c) {
+    const uint32_t col = (uint32_t)(8 * grp) | (uint32_t)((I + c) & 1);
+    const U4 r = philox_lane_c1(s.t_lo, (uint32_t)I * (uint32_t)s.L + col, s.t_hi, 5u | (1u << 3), s.k0, s.k1, rk);
+    return make_uint4(r.x, r.y, r.z, r.w);
+}
+
+}  // namespace ising

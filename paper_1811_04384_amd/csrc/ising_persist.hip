@@ -1,0 +1,361 @@
+// Resident LDS tiles that exchange their boundary columns: many sweeps per
+// launch with no redundant work.
+//
+// Every word row of a band of word columns [c0, c0 + w) of a lattice stays in
+// one workgroup's LDS for all sweeps of a launch, beside two ghost columns
+// (c0 - 1 and c0 + w, modulo L) holding copies of the neighbouring tiles'
+// boundary words.  This is the paper's decomposition (Sections 4 and 5.2,
+// Figs. 3 and 5: each process owns a vertical strip of the word lattice and
+// trades its border columns with the processes beside it), with the
+// workgroups of one GPU in the place of the MPI processes and the
+// checkerboard in the place of the two-phase protocol.  Half-sweep s of
+// colour c in a tile is one pass over its words of colour c:
+//   - the boundary words (local columns 1 and w) come first; each reads its
+//     ghost neighbour straight from the neighbouring tile's publication of
+//     half-sweep s - 1 (from LDS in a launch's first half-sweep), and is
+//     published at once to an exchange buffer in global memory; the thread
+//     that publishes the last of them raises the tile's flag (to a value
+//     that grows with the lattice's sweep counter and the half-sweep);
+//   - then the interior words (columns 2 .. w - 1), while the boundary words
+//     travel, and the Philox blocks of the next half-sweep's position 20;
+//   - at the end, before the workgroup barrier, one thread waits until both
+//     neighbours' flags show this half-sweep (their publications are
+//     normally done long before).
+// Only colour-c words are exchanged, because the next half-sweep only reads
+// those from a ghost column.  The exchange buffer alternates between two
+// halves on the half-sweep's parity: a tile overwrites a half two
+// half-sweeps later, after its neighbours have raised their flags past the
+// half-sweep that read it (each publisher reads its ghost word before it
+// publishes).
+//
+// Every tile of a launch must be resident at once (the host launches at most
+// as many tiles as the device holds).  Each wait is bounded in time: when
+// it expires the launch sets an error word and every tile stops waiting, so
+// a launch always ends; the host reports the error.
+//
+// A lattice with a single tile (w = L) keeps all its columns in LDS and
+// wraps them there: no exchange at all.
+#include <hip/hip_runtime.h>
+
+#include "ising_device.hpp"
+#include "ising_launch.hpp"
+#include "ising_lds_word.hpp"
+#include "ising_moments.hpp"
+
+namespace ising {
+
+namespace {
+
+constexpr int kPersistMaxBlock = 1024;
+constexpr uint32_t kMaxPolls = 1u << 21;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint64_t clock_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+}  // namespace
+
+__global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
+    extern __shared__ uint64_t lds[];
+    __shared__ uint32_t red[2 * (kPersistMaxBlock / 64)];
+    __shared__ int stop;
+    __shared__ uint32_t published;  // boundary words published in this launch
+    const PersistTile tp = a.tiles[blockIdx.x];
+    const LatticeDesc& d = a.descs[tp.lattice];
+    const int L = d.L, N = d.N, istar = d.istar, sh_star = d.sh_star;
+    const int pstar = (L - 1) / N;
+    uint64_t t0;
+    uint32_t t4, t8, k0, k1;
+    if (a.states) {
+        t0 = a.states[tp.lattice].t + a.sweep_off;
+        k0 = d.k0;
+        k1 = d.k1;
+        t4 = d.t4;
+        t8 = d.t8;
+    } else {
+        t0 = a.t0;
+        k0 = a.k0;
+        k1 = a.k1;
+        t4 = a.t4;
+        t8 = a.t8;
+    }
+    const int K = a.K;
+    const bool whole = tp.w >= L;
+    const int w = whole ? L : tp.w;
+    const int width = whole ? L : w + 2;  // local column x <-> global c0 - 1 + x (halo form)
+    const int gx0 = whole ? 0 : (tp.c0 == 0 ? L - 1 : tp.c0 - 1);
+    auto col = [&](int x) {
+        const int u = gx0 + x;
+        return u < L ? u : u - L;
+    };
+    // position-20 blocks: one per (8-column group, row) of the interior
+    // columns, for the current half-sweep
+    const int xi0 = whole ? 0 : 1, xi1 = whole ? L : w + 1;  // interior local columns [xi0, xi1)
+    const int g_lo = col(xi0) >> 3;
+    const int g_hi_raw = col(xi1 - 1) >> 3;
+    // the interior never wraps past the lattice end (tiles start at c0 >= 0
+    // and end at c0 + w <= L), so its groups are g_lo .. g_hi_raw
+    const int n_groups = g_hi_raw - g_lo + 1;
+    uint64_t* __restrict__ T = lds;
+    // two tables [n_groups][N]: this half-sweep's and the next one's
+    uint4* __restrict__ u5tab = reinterpret_cast<uint4*>(lds + (size_t)N * width);
+    const int tid = threadIdx.x, B = blockDim.x;
+    const RoundKeys rk = round_keys(k0, k1);
+    const bool all_blocks = pstar >= 16;
+    auto sweep_of = [&](int hs) {  // half-sweep hs (0-based) of the launch
+        const uint64_t t = t0 + (uint64_t)(hs >> 1);
+        return LdsSweep{L, N, istar, sh_star, pstar, (uint32_t)t, (uint32_t)(t >> 32), k0, k1, t4, t8, all_blocks};
+    };
+    if (tid == 0) {
+        stop = 0;
+        published = 0;
+    }
+
+    // load the band and its ghost columns, eight loads in flight per thread
+    {
+        constexpr int kInFlight = 8;
+        const float rcp = 1.0f / (float)width;
+        const int n = N * width;
+        const uint64_t* __restrict__ G = d.W;
+        for (int i0 = tid; i0 < n; i0 += kInFlight * B) {
+            uint64_t v[kInFlight];
+#pragma unroll
+            for (int k = 0; k < kInFlight; ++k) {
+                const int i = i0 + k * B;
+                if (i < n) {
+                    int I, x;
+                    divmod_small(i, width, rcp, I, x);
+                    v[k] = G[(size_t)((uint32_t)I * (uint32_t)L + (uint32_t)col(x))];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kInFlight; ++k)
+                if (i0 + k * B < n) T[i0 + k * B] = v[k];
+        }
+    }
+    {  // position-20 blocks of the first half-sweep
+        const LdsSweep sw0 = sweep_of(0);
+        const float rcp = 1.0f / (float)n_groups;
+        for (int f = tid; f < N * n_groups; f += B) {
+            int I, k;
+            divmod_small(f, n_groups, rcp, I, k);
+            if (pstar + (I <= istar ? 1 : 0) == 21) u5tab[(size_t)k * N + I] = block5(sw0, rk, I, g_lo + k, 0);
+        }
+    }
+    __syncthreads();
+
+    const int n_hs = 2 * K;
+    const int n_b = whole ? 0 : N;                  // boundary items (columns 1 and w)
+    const int P = whole ? (L >> 1) : ((w - 2) >> 1);  // interior words of a colour per row
+    const int n_i = N * P;
+    const float rcp_P = P > 0 ? 1.0f / (float)P : 0.0f;
+    const float rcp_g = 1.0f / (float)n_groups;
+    const int64_t tw = a.exch_tile_words;
+    for (int hs = 0; hs < n_hs; ++hs) {
+        const int c = hs & 1;
+        const int j = hs >> 1;
+        const LdsSweep sw = sweep_of(hs);
+        const bool meas = c == 1 && a.every > 0 && ((a.sample_base + j + 1) % a.every) == 0;
+        const uint4* __restrict__ u5cur = u5tab + (size_t)(hs & 1) * n_groups * N;
+        uint4* __restrict__ u5next = u5tab + (size_t)((hs + 1) & 1) * n_groups * N;
+        const int n_u = hs + 1 < n_hs ? N * n_groups : 0;
+        const LdsSweep sw_next = sweep_of(hs + 1);
+        // where the neighbours published the ghost words this half-sweep
+        // reads: their boundary words of colour 1 - c, half-sweep hs - 1
+        const uint64_t* __restrict__ gl = a.exch + (size_t)tp.left * tw + (size_t)(1 - c) * 2 * N + N;  // its right side
+        const uint64_t* __restrict__ gr = a.exch + (size_t)tp.right * tw + (size_t)(1 - c) * 2 * N;      // its left side
+        uint64_t* __restrict__ ex = a.exch + (size_t)blockIdx.x * tw + (size_t)c * 2 * N;
+        uint32_t anti = 0, ups = 0;
+        for (int f = tid; f < n_b + n_i + n_u; f += B) {
+            if (f >= n_b + n_i) {  // the next half-sweep's position-20 blocks
+                int I, k;
+                divmod_small(f - n_b - n_i, n_groups, rcp_g, I, k);
+                if (pstar + (I <= istar ? 1 : 0) == 21) u5next[(size_t)k * N + I] = block5(sw_next, rk, I, g_lo + k, c ^ 1);
+                continue;
+            }
+            int I, x, side = -1;
+            if (f < n_b) {  // items f < N/2: column 1 (left side), the others column w (right side)
+                side = f >= (N >> 1) ? 1 : 0;
+                x = side ? w : 1;
+                I = 2 * (f - side * (N >> 1)) + ((col(x) + c) & 1);  // rows with (I + J) % 2 == c
+            } else {
+                int q;
+                divmod_small(f - n_b, P, rcp_P, I, q);
+                x = whole ? 2 * q + ((I + c) & 1) : 2 + 2 * q + ((2 + gx0 + I + c) & 1);
+            }
+            const int J = col(x);
+            const int xl = whole && x == 0 ? L - 1 : x - 1;
+            const int xr = whole && x == L - 1 ? 0 : x + 1;
+            Nbhd nb = lds_nbhd(T, width, N, istar, I, x, xl, xr);
+            if (side >= 0 && hs > 0) {  // the ghost word comes straight from the neighbour's publication
+                if (x == 1) nb.lf = __hip_atomic_load(&gl[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (x == w) nb.rt = __hip_atomic_load(&gr[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            const uint32_t u20 = pick4(u5cur[(size_t)((J >> 3) - g_lo) * N + I], ((uint32_t)J >> 1) & 3u);
+            const uint64_t nw = lds_word_update(sw, rk, nb, I, J, u20, meas, true, anti, ups);
+            T[I * width + x] = nw;
+            if (side >= 0) {
+                // publish; the last of the N boundary words raises the flag
+                // (every publisher waits for its own store first, and the
+                // exchange words and flags are device-coherent atomics, so
+                // no cache writeback or invalidation is needed)
+                __hip_atomic_store(&ex[side * N + I], nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);
+                if (atomicAdd(&published, 1u) == (uint32_t)(hs + 1) * (uint32_t)N - 1u)
+                    __hip_atomic_store(&a.flags[blockIdx.x], 2 * t0 + (uint64_t)hs + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (meas) {
+            anti = wave_sum_u32(anti);
+            ups = wave_sum_u32(ups);
+            if (lane_id() == 0) {
+                red[2 * (tid >> 6)] = anti;
+                red[2 * (tid >> 6) + 1] = ups;
+            }
+        }
+        // before the next half-sweep reads them: both neighbours' boundary
+        // words of this half-sweep must be published
+        if (!whole && tid == 0 && hs + 1 < n_hs) {
+            const uint64_t want = 2 * t0 + (uint64_t)hs + 1;
+            const uint64_t start = clock_ticks();
+            bool ok = true;
+            // bounded twice: by the clock and by the number of polls (each
+            // poll is two loads from memory and a short sleep)
+            for (uint32_t polls = 0; ok; ++polls) {
+                const uint64_t fl = __hip_atomic_load(&a.flags[tp.left], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t fr = __hip_atomic_load(&a.flags[tp.right], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (fl >= want && fr >= want) break;
+                if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                    clock_ticks() - start > a.wait_ticks || polls > kMaxPolls) {
+                    __hip_atomic_store(a.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = false;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (!ok) stop = 1;
+        }
+        __syncthreads();
+        if (meas && tid == 0) {
+            uint32_t sa = 0, su = 0;
+            for (int wv = 0; wv < (B + 63) / 64; ++wv) {
+                sa += red[2 * wv];
+                su += red[2 * wv + 1];
+            }
+            // samples of this launch before this one: multiples of `every` in (sample_base, sample_base + j]
+            const int64_t ord = (a.sample_base + j) / a.every - a.sample_base / a.every;
+            a.partials[(size_t)ord * a.n_tiles + tp.part] = {sa, su};
+        }
+        if (stop) break;
+    }
+    // the ghost columns in LDS are stale past the first half-sweep, but the
+    // band's own words are exact
+
+    // store the band (the ghost columns belong to the neighbours)
+    {
+        const float rcp = 1.0f / (float)w;
+        uint64_t* __restrict__ G = d.W;
+        for (int i = tid; i < N * w; i += B) {
+            int I, xi;
+            divmod_small(i, w, rcp, I, xi);
+            const int x = xi0 + xi;
+            G[(size_t)((uint32_t)I * (uint32_t)L + (uint32_t)col(x))] = T[I * width + x];
+        }
+    }
+}
+
+size_t persist_lds_bytes(int32_t L, int32_t N, int32_t w) {
+    const bool whole = w >= L;
+    const int64_t width = whole ? L : (int64_t)w + 2;
+    const int64_t groups = whole ? (L + 7) / 8 : w / 8 + 2;
+    return (size_t)(8 * (int64_t)N * width + 2 * 16 * groups * (int64_t)N);
+}
+
+size_t persist_lds_limit(int device) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) return 0;
+    const size_t static_bytes = sizeof(uint32_t) * 2 * (kPersistMaxBlock / 64) + 256;
+    return v > (int)static_bytes ? (size_t)v - static_bytes : 0;
+}
+
+hipError_t allow_persist_lds(int device) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persist), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)persist_lds_limit(device));
+}
+
+hipError_t persist_capacity(int block, size_t lds_bytes, int device, int64_t* tiles) {
+    int per_cu = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_persist),
+                                                                block, lds_bytes);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    *tiles = (int64_t)per_cu * cus;
+    return hipSuccess;
+}
+
+hipError_t launch_persist(const PersistLaunch& a, int32_t n_tiles, int block, size_t lds_bytes, hipStream_t s) {
+    if (n_tiles <= 0 || a.K <= 0) return hipSuccess;
+    if (block < 64 || block > kPersistMaxBlock || block % 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_persist, dim3(n_tiles), dim3(block), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ising
+
+namespace ising {
+
+namespace {
+
+// E and M of sample k from the tiles' partial sums (one workgroup per
+// sample): out_E[k], out_M[k].
+__global__ void __launch_bounds__(256) k_samples_em(const Partial* __restrict__ partials, int32_t n_tiles, int32_t L,
+                                                    int64_t* __restrict__ out_E, int64_t* __restrict__ out_M) {
+    __shared__ unsigned long long red[2 * 4];
+    const int k = blockIdx.x;
+    unsigned long long anti = 0, ups = 0;
+    for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
+        const Partial p = partials[(size_t)k * n_tiles + i];
+        anti += p.anti;
+        ups += p.ups;
+    }
+    anti = wave_sum_u64(anti);
+    ups = wave_sum_u64(ups);
+    if (lane_id() == 0) {
+        red[2 * (threadIdx.x >> 6)] = anti;
+        red[2 * (threadIdx.x >> 6) + 1] = ups;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long A = 0, U = 0;
+        for (int wv = 0; wv < (int)(blockDim.x + 63) / 64; ++wv) {
+            A += red[2 * wv];
+            U += red[2 * wv + 1];
+        }
+        const int64_t n = (int64_t)L * (int64_t)L;
+        out_E[k] = 2 * (int64_t)A - 2 * n;
+        out_M[k] = 2 * (int64_t)U - n;
+    }
+}
+
+// Moment sums of n samples, added in order by one thread.
+__global__ void k_samples_moments(const int64_t* __restrict__ E, const int64_t* __restrict__ M, int32_t n,
+                                  Moments* mom) {
+    if (threadIdx.x != 0) return;
+    Moments m = *mom;
+    for (int k = 0; k < n; ++k) add_sample(m, E[k], M[k]);
+    *mom = m;
+}
+
+}  // namespace
+
+hipError_t launch_samples(const Partial* partials, int32_t n_tiles, int32_t n_samples, int32_t L, int64_t* out_E,
+                          int64_t* out_M, Moments* mom, hipStream_t s) {
+    if (n_samples <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_samples_em, dim3(n_samples), dim3(256), 0, s, partials, n_tiles, L, out_E, out_M);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !mom) return e;
+    hipLaunchKernelGGL(k_samples_moments, dim3(1), dim3(64), 0, s, out_E, out_M, n_samples, mom);
+    return hipGetLastError();
+}
+
+}  // namespace ising

@@ -1,7 +1,8 @@
 """GPU parity of the batched form: every lattice of a mixed batch equals the
 oracle (and therefore the same lattice run alone), for every execution plan
-(resident in LDS, resident in global memory, tiled with 1/2/4 words per
-thread, several chunk lengths), including sample series and sums."""
+(resident in LDS, resident in global memory, half-sweep launches with 1/2/4
+words per thread, multi-sweep LDS tiles, several chunk lengths), including
+sample series and sums."""
 import numpy as np
 import pytest
 
@@ -41,6 +42,15 @@ PLANS = [
     dict(resident_max_L=256, resident_block=256, words_per_thread=2, tiled_block=128, sweeps_per_graph=5),
     dict(resident_max_L=1008, resident_block=1024, words_per_thread=4, tiled_block=256, sweeps_per_graph=2),
     dict(resident_max_L=128, resident_block=64, words_per_thread=1, tiled_block=256, sweeps_per_graph=50),
+    # multi-sweep LDS tiles: every lattice (L = 6 whole, the others halo tiles)
+    dict(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=4,
+         tile_max_L=1008, tile_sweeps=2, tile_cols=16, tile_block=256),
+    # resident, tiles and half-sweep launches in one chunk; chunks of 3 + 3
+    dict(resident_max_L=64, resident_block=256, words_per_thread=2, tiled_block=128, sweeps_per_graph=7,
+         tile_max_L=512, tile_sweeps=3, tile_cols=32, tile_block=512),
+    # four sweeps per launch, whole-lattice tiles up to L = 64
+    dict(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=8,
+         tile_max_L=4096, tile_sweeps=4, tile_cols=64, tile_block=1024),
 ]
 
 
@@ -172,5 +182,29 @@ def test_lattice_beyond_4gib_in_a_batch():
         for bad in [(2, 0, 0, 1, 1), (0, 0, 0, 0, 4), (1, 0, 0, 131, 1)]:
             with pytest.raises(ising.IsingError):
                 b.region(*bad)
+    finally:
+        b.close()
+
+
+def test_batch_tiles_sample_every_sweep():
+    """Multi-sweep tiles with a sample after every sweep (several samples per
+    launch, in order) and chunks that are not a multiple of the sweeps per
+    launch: series, sums and states equal the oracle's."""
+    Ls = [1008, 1008, 130, 42, 2016]
+    seeds = [3, 4, 5, 6, 7]
+    Ts = [2.2, 2.4, 2.6, 1.9, 2.269]
+    b = ising.Batch(Ls, seeds, hot=True)
+    try:
+        b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=10,
+                   tile_max_L=2016, tile_sweeps=4, tile_cols=32, tile_block=512)
+        E, M = b.sweep(Ts, 13, every=1, series=True)
+        E, M = E.cpu().numpy(), M.cpu().numpy()
+        res = b.results()
+        for i, (L, seed, T) in enumerate(zip(Ls, seeds, Ts)):
+            s = oracle.init(L, seed, True)
+            Es, Ms = oracle.sweep(s, seed, 0, 13, T, every=1)
+            assert E[i].tolist() == Es.tolist() and M[i].tolist() == Ms.tolist(), i
+            assert (b.spins(i) == s).all(), i
+            assert res["n_samples"][i] == 13 and res["sum_E"][i] == Es.sum()
     finally:
         b.close()

@@ -1,0 +1,158 @@
+"""GPU parity of resident LDS tiles that trade boundary columns (every word
+row of a band of word columns kept in one workgroup's LDS for many sweeps,
+the neighbouring bands' boundary words exchanged through global memory
+every half-sweep) against the CPU oracle.
+
+Bit-exact: the spin state after every call and every sampled E, M equal the
+oracle's.  Cases: the whole lattice in one workgroup (no exchange), many
+bands, two bands (each the other's left and right neighbour), ragged last
+bands down to two columns, L not a multiple of 8 or of 21, the paper's
+L = 21 N lattices, samples spanning launches (calls longer than one launch),
+and workgroups of 64 to 1024 threads.
+"""
+import pytest
+
+import oracle
+import paper_1811_04384_amd as ising
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ising.load()
+
+
+CALLS = [(2.269, 7, 0), (1.5, 10, 3), (3.5, 5, 1), (2.6, 9, 2)]
+
+# (L, seed, hot, tile columns, block, sweeps per launch)
+CASES = [
+    (4, 3, True, 4, 64, 5),
+    (6, 5, False, 6, 64, 3),
+    (42, 7, True, 8, 128, 4),
+    (64, 1234, False, 64, 256, 1000),
+    (84, 9, True, 14, 128, 2),
+    (128, 2, True, 20, 192, 7),
+    (130, 11, True, 16, 256, 3),
+    (252, 12, True, 126, 512, 4),
+    (256, 13, True, 256, 1024, 16),
+    (1006, 4, True, 48, 512, 5),
+    (1008, 21, True, 48, 512, 9),
+    (2016, 22, True, 96, 1024, 4),
+]
+
+
+@pytest.mark.parametrize("L,seed,hot,cols,block,K", CASES)
+def test_resident_tiles_match_oracle(L, seed, hot, cols, block, K):
+    print(f"resident tiles L={L} cols={cols} block={block} K={K}", flush=True)
+    lat = ising.Lattice(L, seed, hot=hot)
+    try:
+        lat.set_resident_tiles(cols, block, K)
+        assert lat.resident_tiles() == (min(cols, L), block, K)
+        s = oracle.init(L, seed, hot)
+        t = 0
+        for T, n, every in CALLS:
+            if every:
+                E, M = lat.sweep_measure(T, n, every)
+                Es, Ms = oracle.sweep(s, seed, t, n, T, every=every)
+                assert E.cpu().numpy().tolist() == Es.tolist(), (T, n, every)
+                assert M.cpu().numpy().tolist() == Ms.tolist(), (T, n, every)
+            else:
+                lat.sweep(T, n)
+                oracle.sweep(s, seed, t, n, T)
+            t += n
+            assert (lat.spins() == s).all(), (T, n, every)
+        assert lat.observables() == oracle.observables(s)
+    finally:
+        lat.close()
+
+
+def test_resident_tiles_moments_and_other_paths():
+    """Resident tiles, half-sweep launches and halo tiles on one sweep
+    counter; moment sums across all three."""
+    L, seed, T = 1008, 31, 2.4
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        lat.set_resident_tiles(64, 512, 4)
+        acc = lat.sweep_moments(T, 6, 1)
+        lat.set_tiling(2, 64, 512)
+        assert lat.resident_tiles() == (0, 0, 0)
+        lat.sweep_moments(T, 5, 1, acc)
+        lat.set_tiling(0)
+        lat.sweep_moments(T, 3, 1, acc)
+        lat.set_resident_tiles(32, 256, 1000)
+        assert lat.tiling() == (0, 0, 0)
+        lat.sweep_moments(T, 7, 1, acc)
+        m = ising.moments_of(acc)
+        spins = lat.spins()
+    finally:
+        lat.close()
+    s = oracle.init(L, seed, True)
+    Es, Ms = oracle.sweep(s, seed, 0, 21, T, every=1)
+    assert m == oracle.moments(Es, Ms)
+    assert (spins == s).all()
+
+
+def test_resident_tiles_l4096_prefix_matches_oracle():
+    """The plain workload's lattice (L = 4096, hot start seed 7, T = 2.269)
+    in 256 bands of 16 columns, E/M every 10 sweeps, 30 sweeps in launches
+    of 20: series and state equal the oracle's."""
+    L, seed, T = 4096, 7, 2.269
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        lat.set_resident_tiles(16, 512, 20)
+        E, M = lat.sweep_measure(T, 30, 10)
+        got = lat.spins()
+        got_E, got_M = E.cpu().numpy().tolist(), M.cpu().numpy().tolist()
+    finally:
+        lat.close()
+    s = oracle.init(L, seed, True)
+    Es, Ms = oracle.sweep(s, seed, 0, 30, T, every=10)
+    assert got_E == Es.tolist() and got_M == Ms.tolist()
+    assert (got == s).all()
+
+
+def test_invalid_resident_tiles_are_rejected():
+    lat = ising.Lattice(4096, 1, hot=True)
+    try:
+        for bad in ((7, 256, 10), (-2, 256, 10), (16, 96, 10), (16, 2048, 10), (16, 256, 0), (16, 256, 5000),
+                    (2, 1024, 10)):  # the last: 2048 bands of 1024 threads exceed what the device holds at once
+            with pytest.raises(ising.IsingError) as e:
+                lat.set_resident_tiles(*bad)
+            assert e.value.code == ising.ISING_EINVAL
+        assert lat.resident_tiles() == (0, 0, 0)
+    finally:
+        lat.close()
+    big = ising.Lattice(32768, 1, hot=False)
+    try:
+        with pytest.raises(ising.IsingError):
+            big.set_resident_tiles(64, 256, 10)  # 1562 word rows: a band does not fit in LDS
+    finally:
+        big.close()
+
+
+def test_resident_tiles_after_reset_and_counter_set_back():
+    """The tiles' flags follow the sweep counter: after ising_reset and a
+    checkpoint restore to an earlier sweep the runs still equal the oracle."""
+    L, seed, T = 1008, 41, 2.3
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        lat.set_resident_tiles(48, 512, 3)
+        lat.sweep(T, 8)
+        lat.reset(seed, hot=True)
+        lat.sweep(T, 5)
+        s = oracle.init(L, seed, True)
+        oracle.sweep(s, seed, 0, 5, T)
+        assert (lat.spins() == s).all()
+        check = lat.spins(), lat.t
+        lat.sweep(T, 7)
+        lat.set_spins(check[0])
+        lat.t = check[1]
+        lat.sweep(T, 4)
+        oracle.sweep(s, seed, 5, 4, T)
+        assert (lat.spins() == s).all() and lat.t == 9
+    finally:
+        lat.close()
