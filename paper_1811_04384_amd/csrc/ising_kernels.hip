@@ -614,13 +614,28 @@ hipError_t set_resident_lds(int wpt, size_t lds_bytes) {
     const void* f = wpt == 1 ? reinterpret_cast<const void*>(&k_resident<1, true>)
                   : wpt == 2 ? reinterpret_cast<const void*>(&k_resident<2, true>)
                              : reinterpret_cast<const void*>(&k_resident<4, true>);
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    int device = 0;
+    if (e == hipSuccess) e = hipGetDevice(&device);
+    if (e == hipSuccess) e = allow_small_lds(device);
+    return e;
 }
 
 hipError_t launch_resident(int wpt, int block, const LatticeDesc* descs, LatticeState* states, const int32_t* ids,
                            int32_t n_ids, int32_t K, int32_t every, size_t lds_bytes, hipStream_t s) {
     if (n_ids <= 0 || K <= 0) return hipSuccess;
     if (block < 64 || block > kResidentMaxBlock || block % 64) return hipErrorInvalidValue;
+    if (lds_bytes > 0) {
+        // lattices small enough to keep the codes of two or more sweeps
+        // beside them in LDS draw those ahead (k_small)
+        int device = 0;
+        hipError_t e = hipGetDevice(&device);
+        if (e != hipSuccess) return e;
+        const size_t limit = small_lds_limit(device);
+        const int32_t batch = lds_bytes < limit ? (int32_t)std::min<size_t>(64, (limit - lds_bytes) / lds_bytes) : 0;
+        if (batch >= 2)
+            return launch_small(block, descs, states, ids, n_ids, K, every, batch, lds_bytes * (1 + batch), s);
+    }
     const dim3 grid(n_ids), blk(block);
 #define ISING_LAUNCH_RES(WPT_)                                                                                  \
     if (lds_bytes > 0) {                                                                                        \

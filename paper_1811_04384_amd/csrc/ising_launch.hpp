@@ -149,6 +149,18 @@ hipError_t launch_persist(const PersistLaunch& a, int32_t n_tiles, int block, si
 hipError_t launch_samples(const Partial* partials, int32_t n_tiles, int32_t n_samples, int32_t L, int64_t* out_E,
                           int64_t* out_M, Moments* mom, hipStream_t s);
 
+// ---- small lattices with their draws taken ahead ----------------------------
+
+// One workgroup per listed lattice, the lattice and the acceptance codes of
+// `batch` sweeps (2..64) in LDS (small_lds_bytes), K sweeps, samples as
+// launch_resident.  launch_resident uses it for LDS-resident lattices whose
+// codes of two or more sweeps fit beside them.
+size_t small_lds_bytes(int32_t L, int32_t N, int32_t batch);
+size_t small_lds_limit(int device);
+hipError_t allow_small_lds(int device);
+hipError_t launch_small(int block, const LatticeDesc* descs, LatticeState* states, const int32_t* ids, int32_t n_ids,
+                        int32_t K, int32_t every, int32_t batch, size_t lds_bytes, hipStream_t s);
+
 // Largest dynamic LDS a resident workgroup may use on this device.
 size_t resident_lds_limit(int device);
 
