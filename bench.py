@@ -243,24 +243,37 @@ def cpu_baseline(target_s=12.0, single_s=4.0):
 
 def run_plain4096(ising, sweeps=10000, every=10):
     """Single lattice L=4096, hot start seed 7, T=2.269, E/M every 10 sweeps,
-    one lattice per launch (the plain form)."""
+    one lattice per launch (the plain form), in the library's default plan
+    for this size (resident tiles: 256 bands of 16 word columns kept in LDS
+    for 1000 sweeps per launch, trading boundary words every half-sweep) and
+    with one launch per half-sweep."""
     import torch
 
-    lat = ising.Lattice(4096, 7, hot=True)
-    lat.sweep_measure(2.269, 100, every)
-    lat.reset(7, hot=True)
-    torch.cuda.synchronize()
-    e0, e1 = _events()
-    e0.record()
-    E, M = lat.sweep_measure(2.269, sweeps, every)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    e = E.double().mean().item() / 4096 ** 2
-    lat.close()
+    def timed(resident):
+        lat = ising.Lattice(4096, 7, hot=True)
+        if not resident:
+            lat.set_resident_tiles(0)
+        plan = {"resident_tiles": lat.resident_tiles(), "half_sweep_plan": lat.plan()}
+        lat.sweep_measure(2.269, 100, every)
+        lat.reset(7, hot=True)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        E, M = lat.sweep_measure(2.269, sweeps, every)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        e = E.double().mean().item() / 4096 ** 2
+        lat.close()
+        return ms, e, plan
+
+    ms, e, plan = timed(True)
+    ms_h, e_h, _ = timed(False)
+    assert e == e_h, "the two plans must give the same series"
     return {"workload": "L=4096 single, hot seed 7, T=2.269, 10000 sweeps, E/M every 10",
             "value": round(4096 ** 2 * sweeps / (ms * 1e6), 2), "unit": UNIT, "ms": round(ms, 2),
-            "mean_e_per_spin": round(e, 6)}
+            "plan": plan, "mean_e_per_spin": round(e, 6),
+            "half_sweep_launches": {"value": round(4096 ** 2 * sweeps / (ms_h * 1e6), 2), "ms": round(ms_h, 2)}}
 
 
 def run_graph4096(ising, sweeps=10000, every=10):
@@ -361,9 +374,10 @@ def run_scan64(ising, therm=2000, meas=2000):
 
     Ts = [1.5 + 2.0 * i / 7 for i in range(8)]
     b = ising.Batch([64] * 8, [1234] * 8, hot=False)
-    # 128 threads: one per word of a colour (N = 4 word rows x 64 columns / 2),
-    # so that each half-sweep is one pass over two wavefronts
-    b.set_plan(resident_max_L=64, resident_block=128, words_per_thread=1, tiled_block=256, sweeps_per_graph=500)
+    # one 512-thread workgroup per lattice, which draws the acceptance codes
+    # of 64 sweeps at a time into LDS and then runs them (the fastest of
+    # 64 .. 1024 threads measured)
+    b.set_plan(resident_max_L=64, resident_block=512, words_per_thread=1, tiled_block=256, sweeps_per_graph=500)
     torch.cuda.synchronize()
     e0, e1 = _events()
     e0.record()
@@ -404,6 +418,12 @@ def run_heating_scan(ising, L=1008, replicas=16, therm=500, meas=1000):
 
     Ts = [round(1.5 + 0.1 * j, 10) for j in range(21)]
     b = ising.Batch([L] * replicas, list(range(replicas)), hot=False)
+    # resident tiles of 64 word columns (16 per lattice, one per compute unit)
+    # that trade boundary words every half-sweep, 200 sweeps per chunk: the
+    # fastest plan measured for this shape (half-sweep launches: 1024 sampled,
+    # 1101 unsampled attempts/ns; these tiles 1349 and 1494)
+    b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=200,
+               tile_max_L=L, tile_sweeps=1, tile_cols=64, tile_block=1024, tile_exchange=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = b.scan(Ts, therm, meas, 1)

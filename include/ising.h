@@ -269,7 +269,10 @@ int ising_get_tiling(ising_lattice* h, int32_t* sweeps_per_launch, int32_t* tile
    device at once.  A launch whose tiles wait for a neighbour longer than
    about a second is abandoned: the next call on the handle returns
    ISING_EHIP, and the lattice state is undefined.  Synchronises.  Results
-   never depend on it.  ising_get_resident_tiles returns zeros when off. */
+   never depend on it.  ising_get_resident_tiles returns zeros when off.
+   ising_create and ising_create_in switch it on for 2560 <= L <= 4608
+   (bands of 2 ceil(L / 512) columns, 1024 threads, 1000 sweeps per launch)
+   when those fit. */
 int ising_set_resident_tiles(ising_lattice* h, int32_t tile_cols, int32_t block, int32_t max_sweeps);
 int ising_get_resident_tiles(ising_lattice* h, int32_t* tile_cols, int32_t* block, int32_t* max_sweeps);
 
@@ -334,9 +337,13 @@ int ising_batch_get_sweep_count(ising_batch* b, int32_t i, uint64_t* t);
 /* Execution plan.  Lattices with L <= resident_max_L are advanced by one
    workgroup each, all their sweeps of a chunk inside one launch, the lattice
    held in LDS when it fits; lattices with resident_max_L < L <= tile_max_L
-   by multi-sweep LDS tiles (tile_sweeps sweeps per launch on tiles of
-   tile_cols word columns with redundant halos, as ising_set_tiling; a
-   lattice whose tile would not fit in LDS goes to the next path); the others
+   by LDS tiles of tile_cols word columns: with tile_exchange = 0,
+   tile_sweeps sweeps per launch on tiles with redundant halos (as
+   ising_set_tiling); with tile_exchange = 1, resident tiles that keep their
+   words in LDS for a whole chunk and trade boundary words every half-sweep
+   (as ising_set_resident_tiles; the lattices whose tiles would exceed what
+   the device holds at once, in index order, go to the next path); a lattice
+   whose tile would not fit in LDS goes to the next path; the others
    by per-half-sweep launches over a table of (lattice, row segment) work
    items with words_per_thread words per thread.  sweeps_per_graph sweeps are
    captured in one hipGraph (rounded to a multiple of `every`).  Results
@@ -351,6 +358,7 @@ typedef struct {
     int32_t tile_sweeps;      /* sweeps per tile launch, 1..16               */
     int32_t tile_cols;        /* interior word columns per tile (even)       */
     int32_t tile_block;       /* threads per tile workgroup (64..1024)       */
+    int32_t tile_exchange;    /* 1: resident tiles trading boundary words    */
 } ising_batch_plan;
 
 /* Validate a plan without a batch (host only, no GPU needed): ISING_OK or
@@ -358,7 +366,8 @@ typedef struct {
    workgroup per lattice is only sensible for lattices that fit, or nearly
    fit, in one workgroup's LDS.  With tile_max_L > 0, tile_sweeps must be in
    [1, 16], tile_cols even and >= 2, tile_block a multiple of 64 in
-   [64, 1024].  ising_batch_set_plan applies the same checks. */
+   [64, 1024], tile_exchange 0 or 1.  ising_batch_set_plan applies the same
+   checks. */
 int ising_batch_check_plan(const ising_batch_plan* plan);
 int ising_batch_set_plan(ising_batch* b, const ising_batch_plan* plan);
 int ising_batch_get_plan(ising_batch* b, ising_batch_plan* plan);

@@ -73,6 +73,17 @@ struct ising_batch {
     int32_t* d_ids_tile = nullptr;
     int32_t n_tile_lat = 0;
     std::vector<std::pair<Geometry, int32_t>> tile_shapes;  // distinct (geometry, tile width) of the tiles
+    // resident tiles trading boundary words (plan.tile_exchange)
+    PersistTile* d_res = nullptr;
+    int32_t n_res = 0;
+    size_t res_lds = 0;
+    uint64_t* d_exch = nullptr;
+    int64_t exch_tile_words = 0;
+    uint64_t* d_flags = nullptr;
+    uint32_t* d_err = nullptr;
+    Partial* d_res_part = nullptr;  // sweeps_per_graph x n_res
+    int32_t* d_ids_res = nullptr;
+    int32_t n_res_lat = 0;
     uint8_t* d_stage = nullptr;  // spin output staging, spin_stage_bytes of the largest L
     size_t stage_bytes = 0;
     std::map<std::pair<int32_t, int32_t>, hipGraphExec_t> graphs;  // (sweeps, every) -> executable
@@ -105,6 +116,12 @@ void release(ising_batch* b) {
     free_dev(b->d_tiles);
     free_dev(b->d_tile_part);
     free_dev(b->d_ids_tile);
+    free_dev(b->d_res);
+    free_dev(b->d_exch);
+    free_dev(b->d_flags);
+    free_dev(b->d_err);
+    free_dev(b->d_res_part);
+    free_dev(b->d_ids_res);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
     if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     if (b->join_ev) (void)hipEventDestroy(b->join_ev);
@@ -136,6 +153,7 @@ int check_plan(const ising_batch_plan& p) {
             return fail(ISING_EINVAL, "plan: tile_sweeps must be in [1, %d]", kTileMaxSweeps);
         if (p.tile_cols < 2 || p.tile_cols % 2) return fail(ISING_EINVAL, "plan: tile_cols must be even and >= 2");
         if (!valid_block(p.tile_block, 1024)) return fail(ISING_EINVAL, "plan: tile_block must be a multiple of 64 in [64, 1024]");
+        if (p.tile_exchange != 0 && p.tile_exchange != 1) return fail(ISING_EINVAL, "plan: tile_exchange must be 0 or 1");
     }
     return ISING_OK;
 }
@@ -201,8 +219,20 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     free_dev(b->d_tiles);
     free_dev(b->d_tile_part);
     free_dev(b->d_ids_tile);
+    free_dev(b->d_res);
+    free_dev(b->d_exch);
+    free_dev(b->d_flags);
+    free_dev(b->d_res_part);
+    free_dev(b->d_ids_res);
+    b->n_res = 0;
+    b->n_res_lat = 0;
+    b->res_lds = 0;
     b->tile_shapes.clear();
     b->plan = p;
+    const size_t res_limit = persist_lds_limit(b->device);
+    std::vector<int32_t> ids_res;
+    std::vector<PersistTile> res_tiles;
+    int32_t res_max_N = 0;
     const size_t lds_limit = resident_lds_limit(b->device);
     const size_t tile_limit = tile_lds_limit(b->device);
     std::vector<int32_t> ids_tile;
@@ -228,7 +258,30 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
             }
             continue;
         }
-        const int32_t tw = g.L <= p.tile_max_L ? tile_width(g, p, tile_limit) : 0;
+        if (g.L <= p.tile_max_L && p.tile_exchange) {
+            // resident tiles, as long as all of them fit on the device at once
+            const int32_t w = p.tile_cols >= g.L ? g.L : p.tile_cols;
+            const size_t lds = persist_lds_bytes(g.L, g.N, w);
+            int64_t capacity = 0;
+            if (lds <= res_limit) ISING_HIP(persist_capacity(p.tile_block, std::max(lds, b->res_lds), b->device, &capacity));
+            const int32_t nt = (g.L + w - 1) / w;
+            if (lds <= res_limit && (int64_t)res_tiles.size() + nt <= capacity) {
+                b->resident[i] = 4;
+                ids_res.push_back(i);
+                b->part_begin[i] = (int32_t)res_tiles.size();
+                b->part_count[i] = nt;
+                const int32_t base = (int32_t)res_tiles.size();
+                for (int32_t t = 0; t < nt; ++t) {
+                    const int32_t c0 = t * w;
+                    res_tiles.push_back({i, c0, std::min(w, g.L - c0), base + (t + nt - 1) % nt, base + (t + 1) % nt,
+                                         base + t});
+                }
+                b->res_lds = std::max(b->res_lds, lds);
+                res_max_N = std::max(res_max_N, g.N);
+                continue;
+            }
+        }
+        const int32_t tw = g.L <= p.tile_max_L && !p.tile_exchange ? tile_width(g, p, tile_limit) : 0;
         if (tw > 0) {
             b->resident[i] = 3;
             ids_tile.push_back(i);
@@ -255,7 +308,9 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     b->n_glb = (int32_t)ids_glb.size();
     b->n_tile_lat = (int32_t)ids_tile.size();
     b->n_tiles = (int32_t)tiles.size();
-    b->n_tiled = b->n - b->n_lds - b->n_glb - b->n_tile_lat;
+    b->n_res_lat = (int32_t)ids_res.size();
+    b->n_res = (int32_t)res_tiles.size();
+    b->n_tiled = b->n - b->n_lds - b->n_glb - b->n_tile_lat - b->n_res_lat;
     b->lds_bytes = max_lds;
     if (!waves.empty()) {
         ISING_HIP(hipMalloc(&b->d_waves, sizeof(WaveItem) * waves.size()));
@@ -270,6 +325,38 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     if (!ids_glb.empty()) {
         ISING_HIP(hipMalloc(&b->d_ids_glb, sizeof(int32_t) * ids_glb.size()));
         ISING_HIP(hipMemcpy(b->d_ids_glb, ids_glb.data(), sizeof(int32_t) * ids_glb.size(), hipMemcpyHostToDevice));
+    }
+    if (!res_tiles.empty()) {
+        // consecutive workgroups go to the 8 XCDs in turn: with a tile count
+        // that is a multiple of 8, give every XCD a run of consecutive tiles
+        // (neighbours then trade words inside one XCD except at run ends)
+        const int32_t n = (int32_t)res_tiles.size();
+        if (n % 8 == 0) {
+            const int32_t m = n / 8;
+            auto block_of = [&](int32_t t) { return 8 * (t % m) + t / m; };
+            std::vector<PersistTile> by_block(n);
+            for (int32_t t = 0; t < n; ++t) {
+                PersistTile q = res_tiles[t];
+                q.left = block_of(q.left);
+                q.right = block_of(q.right);
+                by_block[block_of(t)] = q;
+            }
+            res_tiles.swap(by_block);
+        }
+        ISING_HIP(allow_persist_lds(b->device));
+        b->exch_tile_words = 4 * (int64_t)res_max_N;
+        ISING_HIP(hipMalloc(&b->d_res, sizeof(PersistTile) * res_tiles.size()));
+        ISING_HIP(hipMemcpy(b->d_res, res_tiles.data(), sizeof(PersistTile) * res_tiles.size(), hipMemcpyHostToDevice));
+        ISING_HIP(hipMalloc(&b->d_exch, sizeof(uint64_t) * (size_t)b->exch_tile_words * res_tiles.size()));
+        ISING_HIP(hipMalloc(&b->d_flags, sizeof(uint64_t) * res_tiles.size()));
+        ISING_HIP(hipMemset(b->d_flags, 0, sizeof(uint64_t) * res_tiles.size()));
+        if (!b->d_err) {
+            ISING_HIP(hipMalloc(&b->d_err, sizeof(uint32_t)));
+            ISING_HIP(hipMemset(b->d_err, 0, sizeof(uint32_t)));
+        }
+        ISING_HIP(hipMalloc(&b->d_res_part, sizeof(Partial) * res_tiles.size() * (size_t)p.sweeps_per_graph));
+        ISING_HIP(hipMalloc(&b->d_ids_res, sizeof(int32_t) * ids_res.size()));
+        ISING_HIP(hipMemcpy(b->d_ids_res, ids_res.data(), sizeof(int32_t) * ids_res.size(), hipMemcpyHostToDevice));
     }
     if (!tiles.empty()) {
         ISING_HIP(allow_tile_lds(b->device));
@@ -286,7 +373,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
 // (s + 1) % every == 0) on stream s0, resident work on stream s1.
 int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipStream_t s1) {
     const ising_batch_plan& p = b->plan;
-    const bool fork = (b->n_lds + b->n_glb + b->n_tile_lat) > 0 && b->n_tiled > 0 && s1 != nullptr;
+    const bool fork = (b->n_lds + b->n_glb + b->n_tile_lat + b->n_res_lat) > 0 && b->n_tiled > 0 && s1 != nullptr;
     hipStream_t rs = fork ? s1 : s0;
     if (fork) {
         ISING_HIP(hipEventRecord(b->fork_ev, s0));
@@ -301,6 +388,30 @@ int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipS
     // A measured sweep s is finalized by the next launch on s0: the colour-0
     // half-sweep of sweep s + 1, or the chunk's end.
     auto measured = [&](int32_t s) { return every > 0 && s >= 0 && (s + 1) % every == 0; };
+    // resident tiles: the whole chunk in one launch, its samples finalized
+    // right behind it on the same branch (chunks hold a multiple of `every`
+    // sweeps, so chunk-local sampling is the call's)
+    if (b->n_res_lat) {
+        PersistLaunch a = {};
+        a.tiles = b->d_res;
+        a.descs = b->d_desc;
+        a.states = b->d_state;
+        a.sweep_off = 0;
+        a.K = k;
+        a.every = every;
+        a.sample_base = 0;
+        a.n_tiles = b->n_res;
+        a.partials = b->d_res_part;
+        a.exch = b->d_exch;
+        a.exch_tile_words = b->exch_tile_words;
+        a.flags = b->d_flags;
+        a.error = b->d_err;
+        a.wait_ticks = 100000000ull;  // one second of the 100 MHz clock
+        ISING_HIP(launch_persist(a, b->n_res, p.tile_block, b->res_lds, rs));
+        if (every > 0)
+            ISING_HIP(launch_finalize_resident(b->d_desc, b->d_state, b->d_ids_res, b->n_res_lat, b->d_res_part,
+                                               b->n_res, k / every, rs));
+    }
     // tiles: up to tile_sweeps sweeps per launch, the launch's samples
     // finalized right behind it on the same branch
     for (int32_t done = 0; b->n_tile_lat && done < k;) {
@@ -470,6 +581,7 @@ int create_impl(int32_t n, const int32_t* L, const uint64_t* seed, const int32_t
         p.tile_sweeps = 2;
         p.tile_cols = 16;
         p.tile_block = 256;
+        p.tile_exchange = 0;
     }
     int rc = apply_plan(b, p);
     if (rc != ISING_OK) {
@@ -484,7 +596,7 @@ std::string cache_key(const ising_batch* b) {
     std::map<int32_t, int32_t> hist;
     for (const auto& g : b->geo) hist[g.L] += 1;
     std::ostringstream os;
-    os << b->arch << "|plan2|";
+    os << b->arch << "|plan3|";
     bool first = true;
     for (auto& kv : hist) {
         os << (first ? "" : ",") << kv.first << "x" << kv.second;
@@ -506,9 +618,9 @@ bool cache_lookup(const char* path, const std::string& key, ising_batch_plan* p)
         if (std::sscanf(line.c_str() + at + want.size(),
                         " {\"resident_max_L\": %d, \"resident_block\": %d, \"words_per_thread\": %d, \"tiled_block\": %d, "
                         "\"sweeps_per_graph\": %d, \"tile_max_L\": %d, \"tile_sweeps\": %d, \"tile_cols\": %d, "
-                        "\"tile_block\": %d",
+                        "\"tile_block\": %d, \"tile_exchange\": %d",
                         &q.resident_max_L, &q.resident_block, &q.words_per_thread, &q.tiled_block, &q.sweeps_per_graph,
-                        &q.tile_max_L, &q.tile_sweeps, &q.tile_cols, &q.tile_block) == 9) {
+                        &q.tile_max_L, &q.tile_sweeps, &q.tile_cols, &q.tile_block, &q.tile_exchange) == 10) {
             *p = q;
             return true;
         }
@@ -533,9 +645,9 @@ void cache_store(const char* path, const std::string& key, const ising_batch_pla
     std::snprintf(buf, sizeof buf,
                   "\"%s\": {\"resident_max_L\": %d, \"resident_block\": %d, \"words_per_thread\": %d, \"tiled_block\": "
                   "%d, \"sweeps_per_graph\": %d, \"tile_max_L\": %d, \"tile_sweeps\": %d, \"tile_cols\": %d, "
-                  "\"tile_block\": %d, \"ms_per_sweep\": %.6f}",
+                  "\"tile_block\": %d, \"tile_exchange\": %d, \"ms_per_sweep\": %.6f}",
                   key.c_str(), p.resident_max_L, p.resident_block, p.words_per_thread, p.tiled_block, p.sweeps_per_graph,
-                  p.tile_max_L, p.tile_sweeps, p.tile_cols, p.tile_block, ms);
+                  p.tile_max_L, p.tile_sweeps, p.tile_cols, p.tile_block, p.tile_exchange, ms);
     lines.push_back(buf);
     std::ofstream f(path, std::ios::trunc);
     f << "{\n";
@@ -595,6 +707,18 @@ int ising_batch_sweep(ising_batch* b, const double* T, int64_t n_sweeps, int32_t
     return sweep_impl(b, T, n_sweeps, every, dev_E, dev_M);
 }
 
+// Error left by a resident-tile launch (read after the stream has been
+// synchronised); cleared once reported.
+static int resident_error(ising_batch* b) {
+    if (!b->d_err) return ISING_OK;
+    uint32_t err = 0;
+    ISING_HIP(hipMemcpy(&err, b->d_err, sizeof err, hipMemcpyDeviceToHost));
+    if (!err) return ISING_OK;
+    ISING_HIP(hipMemset(b->d_err, 0, sizeof err));
+    return fail(ISING_EHIP, "batch: a resident-tile launch waited too long for a neighbour tile and was abandoned; "
+                            "the states of its lattices are undefined");
+}
+
 int ising_batch_results(ising_batch* b, int64_t* E, int64_t* M, int64_t* sum_E, int64_t* sum_absM,
                         int64_t* n_samples) {
     if (!b) return fail(ISING_EINVAL, "ising_batch_results: null handle");
@@ -602,6 +726,8 @@ int ising_batch_results(ising_batch* b, int64_t* E, int64_t* M, int64_t* sum_E, 
     std::vector<LatticeState> st(b->n);
     ISING_HIP(hipMemcpyAsync(st.data(), b->d_state, sizeof(LatticeState) * b->n, hipMemcpyDeviceToHost, b->stream));
     ISING_HIP(hipStreamSynchronize(b->stream));
+    const int rc = resident_error(b);
+    if (rc != ISING_OK) return rc;
     for (int32_t i = 0; i < b->n; ++i) {
         if (E) E[i] = st[i].last_E;
         if (M) M[i] = st[i].last_M;
@@ -623,6 +749,8 @@ int ising_batch_moments(ising_batch* b, ising_moments* out) {
     std::vector<LatticeState> st(b->n);
     ISING_HIP(hipMemcpyAsync(st.data(), b->d_state, sizeof(LatticeState) * b->n, hipMemcpyDeviceToHost, b->stream));
     ISING_HIP(hipStreamSynchronize(b->stream));
+    const int rc = resident_error(b);
+    if (rc != ISING_OK) return rc;
     for (int32_t i = 0; i < b->n; ++i) std::memcpy(&out[i], &st[i].mom, sizeof(ising_moments));
     return ISING_OK;
 }
@@ -761,12 +889,27 @@ int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path
                 ising_batch_plan p = half_best;
                 p.resident_max_L = 0;
                 p.tile_max_L = max_L;
+                p.tile_exchange = 0;
                 p.tile_sweeps = K;
                 p.tile_cols = cols;
                 p.tile_block = blk;
                 p.sweeps_per_graph = std::max(K, (std::min(sweeps, 20) / K) * K);
                 rc = consider(p);
             }
+    // 1c) resident tiles trading boundary words (tile width, workgroup size)
+    for (int cols : {16, 32, 64})
+        for (int blk : {256, 512, 1024}) {
+            if (rc != ISING_OK) break;
+            ising_batch_plan p = half_best;
+            p.resident_max_L = 0;
+            p.tile_max_L = max_L;
+            p.tile_exchange = 1;
+            p.tile_sweeps = 1;
+            p.tile_cols = cols;
+            p.tile_block = blk;
+            p.sweeps_per_graph = std::min(sweeps, 50);
+            rc = consider(p);
+        }
     {
         const ising_batch_plan tile_best = best;
         if (tile_best.tile_max_L > 0)

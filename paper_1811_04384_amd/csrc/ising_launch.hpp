@@ -118,6 +118,12 @@ size_t tile_lds_bytes(int32_t L, int32_t N, int32_t w, int32_t K);
 size_t tile_lds_limit(int device);
 hipError_t allow_tile_lds(int device);
 hipError_t launch_tiles(const TileLaunch& a, int32_t n_tiles_launched, int block, size_t lds_bytes, hipStream_t s);
+// The n_samples samples of one resident-tile launch of a batch (partials
+// [sample][tile], a lattice's tiles at part_begin .. + part_count) for the
+// listed lattices: series entries, moment sums, last E and M, in order.
+hipError_t launch_finalize_resident(const LatticeDesc* descs, LatticeState* states, const int32_t* ids,
+                                    int32_t n_lat, const Partial* partials, int32_t n_tiles, int32_t n_samples,
+                                    hipStream_t s);
 // E, M of n_samples samples of one lattice from its tiles' partials, in
 // order: series entries idx0 .. idx0 + n_samples - 1, moment sums, and the
 // last sample into out_EM[0..1] (each optional).
@@ -143,6 +149,12 @@ hipError_t allow_persist_lds(int device);
 // holds at once (a launch must not exceed it).
 hipError_t persist_capacity(int block, size_t lds_bytes, int device, int64_t* tiles);
 hipError_t launch_persist(const PersistLaunch& a, int32_t n_tiles, int block, size_t lds_bytes, hipStream_t s);
+// The n_samples samples of one resident-tile launch of a batch (partials
+// [sample][tile], a lattice's tiles at part_begin .. + part_count) for the
+// listed lattices: series entries, moment sums, last E and M, in order.
+hipError_t launch_finalize_resident(const LatticeDesc* descs, LatticeState* states, const int32_t* ids,
+                                    int32_t n_lat, const Partial* partials, int32_t n_tiles, int32_t n_samples,
+                                    hipStream_t s);
 // E, M of n_samples samples of one lattice from its tiles' partials
 // (sample k in partials[k n_tiles ...]) into out_E[k], out_M[k], then, with
 // mom, added to the moment sums in order.

@@ -348,6 +348,64 @@ __global__ void k_samples_moments(const int64_t* __restrict__ E, const int64_t* 
 
 }  // namespace
 
+namespace {
+
+// The samples of one launch of resident tiles for every tiled lattice of a
+// batch, one wavefront per listed lattice: lane l takes sample base + l (the
+// sum of the lattice's tile partials), then lane 0 adds them in order to the
+// moment sums and the last E, M.
+__global__ void __launch_bounds__(64) k_finalize_resident(const LatticeDesc* __restrict__ descs,
+                                                          LatticeState* __restrict__ states,
+                                                          const int32_t* __restrict__ ids,
+                                                          const Partial* __restrict__ partials, int32_t n_tiles,
+                                                          int32_t n_samples) {
+    __shared__ int64_t sE[64], sM[64];
+    const int32_t lat = ids[blockIdx.x];
+    const LatticeDesc& d = descs[lat];
+    LatticeState& st = states[lat];
+    const int n = min(n_samples, d.sweep_limit);  // a lattice past its limit took fewer samples
+    const int64_t spins = (int64_t)d.L * (int64_t)d.L;
+    const int64_t idx = st.series_idx;
+    for (int base = 0; base < n; base += 64) {
+        const int o = base + lane_id();
+        if (o < n) {
+            unsigned long long anti = 0, ups = 0;
+            const Partial* __restrict__ part = partials + (size_t)o * n_tiles + d.part_begin;
+            for (int i = 0; i < d.part_count; ++i) {
+                anti += part[i].anti;
+                ups += part[i].ups;
+            }
+            const int64_t E = 2 * (int64_t)anti - 2 * spins, M = 2 * (int64_t)ups - spins;
+            sE[lane_id()] = E;
+            sM[lane_id()] = M;
+            if (d.series_E) d.series_E[idx + o] = E;
+            if (d.series_M) d.series_M[idx + o] = M;
+        }
+        __syncthreads();
+        if (lane_id() == 0) {
+            Moments m = st.mom;
+            const int cnt = min(64, n - base);
+            for (int k = 0; k < cnt; ++k) add_sample(m, sE[k], sM[k]);
+            st.mom = m;
+            st.last_E = sE[cnt - 1];
+            st.last_M = sM[cnt - 1];
+        }
+        __syncthreads();
+    }
+    if (lane_id() == 0) st.series_idx = idx + n;
+}
+
+}  // namespace
+
+hipError_t launch_finalize_resident(const LatticeDesc* descs, LatticeState* states, const int32_t* ids,
+                                    int32_t n_lat, const Partial* partials, int32_t n_tiles, int32_t n_samples,
+                                    hipStream_t s) {
+    if (n_lat <= 0 || n_samples <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_resident, dim3(n_lat), dim3(64), 0, s, descs, states, ids, partials, n_tiles,
+                       n_samples);
+    return hipGetLastError();
+}
+
 hipError_t launch_samples(const Partial* partials, int32_t n_tiles, int32_t n_samples, int32_t L, int64_t* out_E,
                           int64_t* out_M, Moments* mom, hipStream_t s) {
     if (n_samples <= 0) return hipSuccess;

@@ -51,6 +51,12 @@ PLANS = [
     # four sweeps per launch, whole-lattice tiles up to L = 64
     dict(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=8,
          tile_max_L=4096, tile_sweeps=4, tile_cols=64, tile_block=1024),
+    # resident tiles trading boundary words: every lattice (L = 6, 42 whole)
+    dict(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=4,
+         tile_max_L=1008, tile_sweeps=1, tile_cols=48, tile_block=512, tile_exchange=1),
+    # resident lattices, resident tiles (two-column bands) and half-sweep launches in one chunk
+    dict(resident_max_L=64, resident_block=256, words_per_thread=2, tiled_block=128, sweeps_per_graph=6,
+         tile_max_L=512, tile_sweeps=1, tile_cols=2, tile_block=64, tile_exchange=1),
 ]
 
 
@@ -197,6 +203,29 @@ def test_batch_tiles_sample_every_sweep():
     try:
         b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=10,
                    tile_max_L=2016, tile_sweeps=4, tile_cols=32, tile_block=512)
+        E, M = b.sweep(Ts, 13, every=1, series=True)
+        E, M = E.cpu().numpy(), M.cpu().numpy()
+        res = b.results()
+        for i, (L, seed, T) in enumerate(zip(Ls, seeds, Ts)):
+            s = oracle.init(L, seed, True)
+            Es, Ms = oracle.sweep(s, seed, 0, 13, T, every=1)
+            assert E[i].tolist() == Es.tolist() and M[i].tolist() == Ms.tolist(), i
+            assert (b.spins(i) == s).all(), i
+            assert res["n_samples"][i] == 13 and res["sum_E"][i] == Es.sum()
+    finally:
+        b.close()
+
+
+def test_batch_resident_tiles_sample_every_sweep():
+    """Resident tiles with a sample after every sweep (many samples per
+    launch, in order): series, sums and states equal the oracle's."""
+    Ls = [1008, 1008, 130, 42, 2016]
+    seeds = [3, 4, 5, 6, 7]
+    Ts = [2.2, 2.4, 2.6, 1.9, 2.269]
+    b = ising.Batch(Ls, seeds, hot=True)
+    try:
+        b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=10,
+                   tile_max_L=2016, tile_sweeps=1, tile_cols=32, tile_block=512, tile_exchange=1)
         E, M = b.sweep(Ts, 13, every=1, series=True)
         E, M = E.cpu().numpy(), M.cpu().numpy()
         res = b.results()
