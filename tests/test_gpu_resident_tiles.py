@@ -118,11 +118,15 @@ def test_resident_tiles_l4096_prefix_matches_oracle():
 def test_invalid_resident_tiles_are_rejected():
     lat = ising.Lattice(4096, 1, hot=True)
     try:
+        default = lat.resident_tiles()
+        assert default == (16, 1024, 1000)  # the library's default for this size
         for bad in ((7, 256, 10), (-2, 256, 10), (16, 96, 10), (16, 2048, 10), (16, 256, 0), (16, 256, 5000),
                     (2, 1024, 10)):  # the last: 2048 bands of 1024 threads exceed what the device holds at once
             with pytest.raises(ising.IsingError) as e:
                 lat.set_resident_tiles(*bad)
             assert e.value.code == ising.ISING_EINVAL
+        assert lat.resident_tiles() == default  # a refused setting leaves the plan as it was
+        lat.set_resident_tiles(0)
         assert lat.resident_tiles() == (0, 0, 0)
     finally:
         lat.close()
