@@ -309,10 +309,11 @@ def batched_config():
     return Ls, Ts, seeds
 
 
-def run_batched(ising, sweeps=5000, every=10):
+def run_batched(ising, sweeps=5000, every=10, autotune=True):
     """2048 lattices, L in {256, 512, 1024, 2048} (512 each), 32 temperatures
     over [1.5, 3.5], hot start seed = index, 5000 sweeps, E/M every 10; the
-    plan from the autotuner, chunks replayed as hipGraphs."""
+    plan from the autotuner (or the default plan), chunks replayed as
+    hipGraphs."""
     import torch
 
     Ls, Ts, seeds = batched_config()
@@ -320,7 +321,7 @@ def run_batched(ising, sweeps=5000, every=10):
     cache = os.path.join(os.path.expanduser("~"), ".cache", "ising_msc", "tune.json")
     os.makedirs(os.path.dirname(cache), exist_ok=True)
     t_tune = time.perf_counter()
-    plan = b.autotune(Ts, cache)
+    plan = b.autotune(Ts, cache) if autotune else b.plan()
     t_tune = time.perf_counter() - t_tune
     torch.cuda.synchronize()
     e0, e1 = _events()
@@ -334,7 +335,8 @@ def run_batched(ising, sweeps=5000, every=10):
     b.close()
     value = spins * sweeps / (ms * 1e6)
     plain = run_batched_as_plain(ising, Ls, Ts, seeds, every=every)
-    return {"workload": "2048 lattices L in {256,512,1024,2048}, 32 T in [1.5,3.5], hot, 5000 sweeps, E/M every 10",
+    return {"workload": f"2048 lattices L in {{256,512,1024,2048}}, 32 T in [1.5,3.5], hot, {sweeps} sweeps, "
+                        f"E/M every 10",
             "value": round(value, 2), "unit": UNIT, "ms": round(ms, 1), "plan": plan,
             "autotune_s": round(t_tune, 2), "samples_per_lattice": int(res["n_samples"][0]),
             "plain_same_mix": plain, "batched_over_plain": round(value / plain["value"], 2)}
@@ -605,6 +607,31 @@ def run_serving_bounded(ising, rates=(25.0, 50.0, 75.0), duration=10.0, quantum=
                         f"quantum {quantum}", "highest_bounded_rate_req_s": best, "runs": runs, "unit": UNIT}
 
 
+def run_secondary(ising, name, args):
+    if name == "plain4096":
+        return run_plain4096(ising)
+    if name == "graph4096":
+        return run_graph4096(ising)
+    if name == "batched":
+        return run_batched(ising, sweeps=args.batched_sweeps, autotune=not args.no_autotune)
+    if name == "scan64":
+        return run_scan64(ising)
+    if name == "heating_scan":
+        return run_heating_scan(ising)
+    if name == "paper_scan":
+        return run_paper_scan(ising)
+    if name == "paper_cases":
+        return run_paper_cases(ising)
+    if name == "replicas":
+        return run_replicas(ising)
+    if name == "serving_bounded":
+        return run_serving_bounded(ising)
+    if name == "serving":
+        return run_serving(ising, args.serving_rate, args.serving_duration, args.serving_quantum,
+                           slots=args.serving_slots)
+    raise SystemExit(f"unknown workload {name}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -629,6 +656,13 @@ def main():
                          "vector instructions the half-sweep uses) and print its JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run 10 device-to-device copies of BYTES bytes (HBM counter calibration)")
+    ap.add_argument("--only", default="", metavar="WORKLOADS",
+                    help="run only these comma-separated secondary workloads (no headline, no CPU baseline) and "
+                         "print one JSON line with their results (for profiling one kernel at a time)")
+    ap.add_argument("--batched-sweeps", type=int, default=5000,
+                    help="sweeps of the batched mix (5000 as specified; fewer for a profiling run)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the batched mix in its default plan instead of the autotuned one")
     ap.add_argument("--build-valu-rates", action="store_true",
                     help="only compile the instruction-rate microbenchmark (no GPU needed) and exit")
     args = ap.parse_args()
@@ -684,6 +718,15 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 10}), flush=True)
         return
 
+    if args.only:
+        out = {}
+        for name in args.only.split(","):
+            log(f"only: {name}")
+            out[name] = run_secondary(ising, name, args)
+            log(f"  {out[name]}")
+        print(json.dumps({"only": out}), flush=True)
+        return
+
     log(f"headline: L={L_MAIN} x T={TEMPS_MAIN} x {args.sweeps} sweeps, warmup {args.warmup}, steps {args.steps}")
     main_res = run_main(ising, args.steps, args.warmup, args.sweeps)
     log(f"headline: {main_res['value']:.1f} attempts/ns, {main_res['ms_per_step']:.1f} ms/step")
@@ -693,27 +736,7 @@ def main():
     wanted = [] if args.secondary == "none" else args.secondary.split(",")
     for name in wanted:
         log(f"secondary: {name}")
-        if name == "plain4096":
-            secondary[name] = run_plain4096(ising)
-        elif name == "graph4096":
-            secondary[name] = run_graph4096(ising)
-        elif name == "batched":
-            secondary[name] = run_batched(ising)
-        elif name == "scan64":
-            secondary[name] = run_scan64(ising)
-        elif name == "heating_scan":
-            secondary[name] = run_heating_scan(ising)
-        elif name == "paper_scan":
-            secondary[name] = run_paper_scan(ising)
-        elif name == "paper_cases":
-            secondary[name] = run_paper_cases(ising)
-        elif name == "replicas":
-            secondary[name] = run_replicas(ising)
-        elif name == "serving_bounded":
-            secondary[name] = run_serving_bounded(ising)
-        elif name == "serving":
-            secondary[name] = run_serving(ising, args.serving_rate, args.serving_duration, args.serving_quantum,
-                                          slots=args.serving_slots)
+        secondary[name] = run_secondary(ising, name, args)
         log(f"  {secondary.get(name)}")
 
     cpu = None
