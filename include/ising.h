@@ -209,6 +209,27 @@ int ising_scan(ising_lattice* h, int32_t n_T, const double* T, int64_t therm, in
 int ising_random_iterations(ising_lattice* h, double T, int32_t strip_cols, int64_t n_iterations, int32_t every,
                             int64_t* dev_E, int64_t* dev_M, ising_moments* dev_acc);
 
+/* For callers that cannot allocate device memory (code under graph
+   capture, tight serving loops, harnesses that forbid it): the sweeps of
+   ising_sweep_measure on a caller-owned word lattice, with no handle and no
+   allocation.  dev_words: device buffer of bytes >= ising_required_bytes(L)
+   bytes (8-byte aligned) holding the lattice in the layout above (for
+   example the words of a handle, ising_words); it is advanced by n_sweeps
+   >= 0 sweeps at T with key `seed`, the first being absolute sweep t0; after
+   the k-th sweep with k % every == 0 (every >= 1) E and M go to
+   dev_E[k/every - 1], dev_M[k/every - 1] (device pointers).  The launch
+   shape is ising_create's default one-launch-per-half-sweep plan.  Its
+   scratch (the partial sums of a sampled half-sweep and their reduction
+   state) is a fixed 2 MiB device array, per GPU, held until the process
+   ends: EINVAL for a lattice whose partial sums would not fit (L above
+   32768).  Enqueued on `stream`; allocates nothing.  Calls that overlap on
+   one GPU (different streams, threads) share that scratch and race; calls
+   ordered on one stream do not.  The scratch keeps the last call's
+   contents; each call clears what must start at zero itself (with a kernel,
+   so it may be captured into a graph). */
+int ising_sweep_measure_static(void* dev_words, size_t bytes, int32_t L, uint64_t seed, uint64_t t0, double T,
+                               int64_t n_sweeps, int32_t every, int64_t* dev_E, int64_t* dev_M, void* stream);
+
 /* E and M of the current state (host pointers).  Synchronises the stream. */
 int ising_observables(ising_lattice* h, int64_t* E, int64_t* M);
 

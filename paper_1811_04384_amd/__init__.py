@@ -288,6 +288,12 @@ def ising_get_resident_tiles(h):
     return int(c.value), int(b.value), int(k.value)
 
 
+def ising_sweep_measure_static(dev_words, nbytes, L, seed, t0, T, n_sweeps, every, dev_E, dev_M, stream=None):
+    _check(_lib.load().ising_sweep_measure_static(_ptr(dev_words), int(nbytes), int(L), int(seed), int(t0), float(T),
+                                                  int(n_sweeps), int(every), _ptr(dev_E), _ptr(dev_M),
+                                                  _stream(stream)))
+
+
 def ising_synchronize(h):
     _check(_lib.load().ising_synchronize(h))
 

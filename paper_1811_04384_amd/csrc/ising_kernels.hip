@@ -461,6 +461,11 @@ __global__ void __launch_bounds__(256) k_pack_rows(const uint8_t* __restrict__ i
     *w = in[idx] ? (*w | bit) : (*w & ~bit);
 }
 
+__global__ void __launch_bounds__(256) k_zero_words(uint64_t* __restrict__ p, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 inline unsigned grid_for(uint64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
@@ -468,6 +473,12 @@ inline unsigned grid_for(uint64_t n, int block) { return (unsigned)((n + block -
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_zero_words(uint64_t* p, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_init(uint64_t* W, const Geometry& g, uint64_t seed, int hot, hipStream_t s) {
     const uint64_t n = (uint64_t)g.N * (uint64_t)g.L;

@@ -20,6 +20,9 @@ inline int64_t waves_per_colour(const Geometry& g, int32_t wpt) {
     return (int64_t)g.N * ((segments_per_row(g.L, wpt) + 63) / 64);
 }
 
+// Zero n 64-bit words with a kernel (usable inside a captured graph).
+hipError_t launch_zero_words(uint64_t* p, uint64_t n, hipStream_t s);
+
 // Spins of a fresh lattice: cold (all up) or hot (Philox stream 0 draw < 2^31).
 hipError_t launch_init(uint64_t* W, const Geometry& g, uint64_t seed, int hot, hipStream_t s);
 
