@@ -370,16 +370,17 @@ def run_batched_as_plain(ising, Ls, Ts, seeds, sweeps=2000, every=10):
 
 def run_scan64(ising, therm=2000, meas=2000):
     """L=64, cold start, 8 temperatures over [1.5, 3.5], seed 1234, 2000 + 2000
-    sweeps (sample every measured sweep): batched (one workgroup per lattice,
-    LDS-resident) and as 8 plain lattices."""
+    sweeps (sample every measured sweep): batched (codes drawn chip-wide, one
+    workgroup per lattice applying them in LDS) and as 8 plain lattices."""
     import torch
 
     Ts = [1.5 + 2.0 * i / 7 for i in range(8)]
     b = ising.Batch([64] * 8, [1234] * 8, hot=False)
-    # one 512-thread workgroup per lattice, which draws the acceptance codes
-    # of 64 sweeps at a time into LDS and then runs them (the fastest of
-    # 64 .. 1024 threads measured)
-    b.set_plan(resident_max_L=64, resident_block=512, words_per_thread=1, tiled_block=256, sweeps_per_graph=500)
+    # the acceptance codes of 2000 sweeps drawn over the whole chip, then
+    # applied by one two-wavefront workgroup per lattice (62 attempts/ns
+    # measured; drawing them inside each lattice's own workgroup: 16)
+    b.set_plan(resident_max_L=64, resident_block=128, words_per_thread=1, tiled_block=256, sweeps_per_graph=2000,
+               draw_sweeps=2000)
     torch.cuda.synchronize()
     e0, e1 = _events()
     e0.record()

@@ -367,8 +367,14 @@ int ising_batch_get_sweep_count(ising_batch* b, int32_t i, uint64_t* t);
    whose tile would not fit in LDS goes to the next path; the others
    by per-half-sweep launches over a table of (lattice, row segment) work
    items with words_per_thread words per thread.  sweeps_per_graph sweeps are
-   captured in one hipGraph (rounded to a multiple of `every`).  Results
-   never depend on the plan. */
+   captured in one hipGraph (rounded to a multiple of `every`).  With
+   draw_sweeps > 0, resident lattices with at most 4 x min(resident_block,
+   256) words of a colour (L up to 128 with 256 threads) instead have their
+   acceptance codes (which do not depend on the spins, Table 1) drawn by a
+   launch spread over the whole chip, draw_sweeps sweeps at a time (a
+   device buffer of draw_sweeps x 8 x their words bytes, capped at
+   256 MiB), and applied by one workgroup of min(resident_block, 256)
+   threads per lattice.  Results never depend on the plan. */
 typedef struct {
     int32_t resident_max_L;   /* 0 = no resident lattices                    */
     int32_t resident_block;   /* threads per resident workgroup (64..1024)   */
@@ -380,6 +386,7 @@ typedef struct {
     int32_t tile_cols;        /* interior word columns per tile (even)       */
     int32_t tile_block;       /* threads per tile workgroup (64..1024)       */
     int32_t tile_exchange;    /* 1: resident tiles trading boundary words    */
+    int32_t draw_sweeps;      /* 0, or sweeps per chip-wide draw (1..4096)   */
 } ising_batch_plan;
 
 /* Validate a plan without a batch (host only, no GPU needed): ISING_OK or
@@ -387,8 +394,8 @@ typedef struct {
    workgroup per lattice is only sensible for lattices that fit, or nearly
    fit, in one workgroup's LDS.  With tile_max_L > 0, tile_sweeps must be in
    [1, 16], tile_cols even and >= 2, tile_block a multiple of 64 in
-   [64, 1024], tile_exchange 0 or 1.  ising_batch_set_plan applies the same
-   checks. */
+   [64, 1024], tile_exchange 0 or 1.  draw_sweeps must be in [0, 4096].
+   ising_batch_set_plan applies the same checks. */
 int ising_batch_check_plan(const ising_batch_plan* plan);
 int ising_batch_set_plan(ising_batch* b, const ising_batch_plan* plan);
 int ising_batch_get_plan(ising_batch* b, ising_batch_plan* plan);

@@ -17,7 +17,8 @@ ISING_COLD, ISING_HOT = 0, 1
 class BatchPlan(ctypes.Structure):
     _fields_ = [("resident_max_L", c_i32), ("resident_block", c_i32), ("words_per_thread", c_i32),
                 ("tiled_block", c_i32), ("sweeps_per_graph", c_i32), ("tile_max_L", c_i32), ("tile_sweeps", c_i32),
-                ("tile_cols", c_i32), ("tile_block", c_i32), ("tile_exchange", c_i32)]
+                ("tile_cols", c_i32), ("tile_block", c_i32), ("tile_exchange", c_i32),
+                ("draw_sweeps", c_i32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -14,7 +14,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libising.so")
 ARCH = "gfx950"
 
-SOURCES = [s for s in ["ising_kernels.hip", "ising_tiles.hip", "ising_persist.hip", "ising_small.hip", "ising_static.hip",
+SOURCES = [s for s in ["ising_kernels.hip", "ising_tiles.hip", "ising_persist.hip", "ising_small.hip", "ising_drawahead.hip",
+                       "ising_static.hip",
                        "ising_strips.hip", "ising_replicas.hip",
                        "ising_lattice.cpp",
                        "ising_batch.cpp", "ising_server.cpp", "ising_replicas.cpp"]

@@ -53,7 +53,8 @@ struct ising_batch {
     std::vector<uint64_t> t_host;
     ising_batch_plan plan{};
     // derived from the plan
-    std::vector<int32_t> resident;  // 0 half-sweep launches, 1 resident in LDS, 2 resident in global memory, 3 tiles
+    std::vector<int32_t> resident;  // 0 half-sweep launches, 1 resident in LDS, 2 resident in global memory, 3 tiles,
+                                    // 4 resident tiles, 5 codes drawn chip-wide
     std::vector<int64_t> units;
     std::vector<int32_t> part_begin, part_count;
     WaveItem* d_waves = nullptr;
@@ -84,6 +85,14 @@ struct ising_batch {
     Partial* d_res_part = nullptr;  // sweeps_per_graph x n_res
     int32_t* d_ids_res = nullptr;
     int32_t n_res_lat = 0;
+    // small resident lattices whose codes are drawn chip-wide (plan.draw_sweeps)
+    DrawLat* d_draw = nullptr;
+    int32_t n_draw = 0;
+    int32_t draw_max_items = 0;  // largest n_draw of the list
+    int32_t draw_S = 0;          // sweeps per draw pass
+    int32_t draw_wmax = 0;       // words of a colour per thread of an apply workgroup
+    size_t draw_lds = 0;
+    uint64_t* d_codes = nullptr;
     uint8_t* d_stage = nullptr;  // spin output staging, spin_stage_bytes of the largest L
     size_t stage_bytes = 0;
     std::map<std::pair<int32_t, int32_t>, hipGraphExec_t> graphs;  // (sweeps, every) -> executable
@@ -122,6 +131,8 @@ void release(ising_batch* b) {
     free_dev(b->d_err);
     free_dev(b->d_res_part);
     free_dev(b->d_ids_res);
+    free_dev(b->d_draw);
+    free_dev(b->d_codes);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
     if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     if (b->join_ev) (void)hipEventDestroy(b->join_ev);
@@ -138,6 +149,9 @@ size_t lattice_bytes(const Geometry& g) { return (size_t)g.N * (size_t)g.L * siz
 // and are already far slower with one workgroup each than tiled; larger ones
 // would put a multi-gigabyte lattice on a single workgroup.
 constexpr int32_t kResidentMaxL = 4096;
+// Sweeps per chip-wide draw pass, and the largest code buffer it may use.
+constexpr int32_t kMaxDrawSweeps = 4096;
+constexpr size_t kMaxDrawBytes = size_t(256) << 20;
 
 int check_plan(const ising_batch_plan& p) {
     if (p.resident_max_L < 0 || p.resident_max_L > kResidentMaxL)
@@ -148,6 +162,8 @@ int check_plan(const ising_batch_plan& p) {
     if (!valid_block(p.tiled_block, 256)) return fail(ISING_EINVAL, "plan: tiled_block must be a multiple of 64 in [64, 256]");
     if (p.sweeps_per_graph < 1 || p.sweeps_per_graph > 100000) return fail(ISING_EINVAL, "plan: sweeps_per_graph must be in [1, 100000]");
     if (p.tile_max_L < 0 || p.tile_max_L > kMaxL) return fail(ISING_EINVAL, "plan: tile_max_L must be in [0, %d]", kMaxL);
+    if (p.draw_sweeps < 0 || p.draw_sweeps > kMaxDrawSweeps)
+        return fail(ISING_EINVAL, "plan: draw_sweeps must be in [0, %d]", kMaxDrawSweeps);
     if (p.tile_max_L > 0) {
         if (p.tile_sweeps < 1 || p.tile_sweeps > kTileMaxSweeps)
             return fail(ISING_EINVAL, "plan: tile_sweeps must be in [1, %d]", kTileMaxSweeps);
@@ -165,6 +181,9 @@ int32_t tile_width(const Geometry& g, const ising_batch_plan& p, size_t lds_limi
     if (w < g.L && w + 4 * p.tile_sweeps > g.L) w = g.L;  // the halos would overlap: whole lattice
     return tile_lds_bytes(g.L, g.N, w, p.tile_sweeps) <= lds_limit ? w : 0;
 }
+
+// Threads per apply workgroup of the lattices whose codes are drawn chip-wide.
+int32_t apply_block(const ising_batch_plan& p) { return std::min(p.resident_block, 256); }
 
 size_t tile_launch_lds(const ising_batch* b, int32_t K) {
     size_t m = 0;
@@ -224,6 +243,9 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     free_dev(b->d_flags);
     free_dev(b->d_res_part);
     free_dev(b->d_ids_res);
+    free_dev(b->d_draw);
+    free_dev(b->d_codes);
+    b->n_draw = 0;
     b->n_res = 0;
     b->n_res_lat = 0;
     b->res_lds = 0;
@@ -241,14 +263,18 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     b->units.assign(b->n, 0);
     b->part_begin.assign(b->n, 0);
     b->part_count.assign(b->n, 0);
-    std::vector<int32_t> ids_lds, ids_glb;
+    std::vector<int32_t> ids_lds, ids_glb, ids_draw;
     std::vector<WaveItem> waves;
     size_t max_lds = 0;
     b->off32 = true;
     for (int32_t i = 0; i < b->n; ++i) {
         const Geometry& g = b->geo[i];
         if (g.L <= p.resident_max_L) {
-            if (lattice_bytes(g) <= lds_limit) {
+            if (p.draw_sweeps > 0 && wave_apply_words_per_thread(g.L, g.N, apply_block(p)) > 0 &&
+                wave_apply_lds_bytes(g.N * g.L, p.draw_sweeps) <= lds_limit) {
+                b->resident[i] = 5;
+                ids_draw.push_back(i);
+            } else if (lattice_bytes(g) <= lds_limit) {
                 b->resident[i] = 1;
                 ids_lds.push_back(i);
                 max_lds = std::max(max_lds, lattice_bytes(g));
@@ -310,7 +336,8 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     b->n_tiles = (int32_t)tiles.size();
     b->n_res_lat = (int32_t)ids_res.size();
     b->n_res = (int32_t)res_tiles.size();
-    b->n_tiled = b->n - b->n_lds - b->n_glb - b->n_tile_lat - b->n_res_lat;
+    b->n_draw = (int32_t)ids_draw.size();
+    b->n_tiled = b->n - b->n_lds - b->n_glb - b->n_tile_lat - b->n_res_lat - b->n_draw;
     b->lds_bytes = max_lds;
     if (!waves.empty()) {
         ISING_HIP(hipMalloc(&b->d_waves, sizeof(WaveItem) * waves.size()));
@@ -358,6 +385,33 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
         ISING_HIP(hipMalloc(&b->d_ids_res, sizeof(int32_t) * ids_res.size()));
         ISING_HIP(hipMemcpy(b->d_ids_res, ids_res.data(), sizeof(int32_t) * ids_res.size(), hipMemcpyHostToDevice));
     }
+    if (!ids_draw.empty()) {
+        // codes of draw_S sweeps of every such lattice per draw pass
+        std::vector<DrawLat> dl;
+        int64_t words = 0;
+        int32_t max_NL = 0;
+        b->draw_max_items = 0;
+        b->draw_wmax = 1;
+        for (int32_t i : ids_draw) {
+            const Geometry& g = b->geo[i];
+            dl.push_back({i, 2 * g.N * ((g.L + 7) / 8), 0});
+            words += (int64_t)g.N * g.L;
+            max_NL = std::max(max_NL, g.N * g.L);
+            b->draw_max_items = std::max(b->draw_max_items, dl.back().n_draw);
+            b->draw_wmax = std::max(b->draw_wmax, wave_apply_words_per_thread(g.L, g.N, apply_block(p)));
+        }
+        b->draw_S = (int32_t)std::min<int64_t>(p.draw_sweeps, std::max<int64_t>(1, (int64_t)(kMaxDrawBytes / 8) / words));
+        int64_t base = 0;
+        for (auto& e : dl) {
+            e.base = base;
+            base += (int64_t)b->draw_S * b->geo[e.lat].N * b->geo[e.lat].L;
+        }
+        b->draw_lds = wave_apply_lds_bytes(max_NL, b->draw_S);
+        ISING_HIP(allow_wave_apply_lds(b->device));
+        ISING_HIP(hipMalloc(&b->d_draw, sizeof(DrawLat) * dl.size()));
+        ISING_HIP(hipMemcpy(b->d_draw, dl.data(), sizeof(DrawLat) * dl.size(), hipMemcpyHostToDevice));
+        ISING_HIP(hipMalloc(&b->d_codes, sizeof(uint64_t) * (size_t)base));
+    }
     if (!tiles.empty()) {
         ISING_HIP(allow_tile_lds(b->device));
         ISING_HIP(hipMalloc(&b->d_tiles, sizeof(TileWork) * tiles.size()));
@@ -373,7 +427,8 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
 // (s + 1) % every == 0) on stream s0, resident work on stream s1.
 int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipStream_t s1) {
     const ising_batch_plan& p = b->plan;
-    const bool fork = (b->n_lds + b->n_glb + b->n_tile_lat + b->n_res_lat) > 0 && b->n_tiled > 0 && s1 != nullptr;
+    const bool fork =
+        (b->n_lds + b->n_glb + b->n_tile_lat + b->n_res_lat + b->n_draw) > 0 && b->n_tiled > 0 && s1 != nullptr;
     hipStream_t rs = fork ? s1 : s0;
     if (fork) {
         ISING_HIP(hipEventRecord(b->fork_ev, s0));
@@ -385,6 +440,14 @@ int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipS
     if (b->n_glb)
         ISING_HIP(launch_resident(p.words_per_thread, p.resident_block, b->d_desc, b->d_state, b->d_ids_glb, b->n_glb,
                                   k, every, 0, rs));
+    // codes drawn chip-wide, then applied, draw_S sweeps at a time
+    for (int32_t done = 0; b->n_draw && done < k; done += b->draw_S) {
+        const int32_t S = std::min(b->draw_S, k - done);
+        ISING_HIP(launch_draw_codes(b->d_desc, b->d_state, b->d_draw, b->n_draw, b->draw_max_items, b->d_codes, done,
+                                    S, rs));
+        ISING_HIP(launch_wave_apply(b->draw_wmax, apply_block(p), b->d_desc, b->d_state, b->d_draw, b->n_draw,
+                                    b->d_codes, done, S, every, b->draw_lds, rs));
+    }
     // A measured sweep s is finalized by the next launch on s0: the colour-0
     // half-sweep of sweep s + 1, or the chunk's end.
     auto measured = [&](int32_t s) { return every > 0 && s >= 0 && (s + 1) % every == 0; };
@@ -582,6 +645,20 @@ int create_impl(int32_t n, const int32_t* L, const uint64_t* seed, const int32_t
         p.tile_cols = 16;
         p.tile_block = 256;
         p.tile_exchange = 0;
+        // the smallest lattices (up to 1024 words of a colour) have their
+        // codes drawn chip-wide; a batch of nothing else runs 500 sweeps per
+        // graph (8 x L = 64 to 2048 x L = 64 measured 2-4x faster than
+        // drawing in each lattice's workgroup)
+        p.draw_sweeps = 0;
+        bool all_drawn = true;
+        for (int32_t i = 0; i < n; ++i) {
+            const Geometry& g = b->geo[i];
+            const bool drawn = g.L <= p.resident_max_L && wave_apply_words_per_thread(g.L, g.N, 256) > 0 &&
+                               wave_apply_lds_bytes(g.N * g.L, 500) <= lim;
+            if (drawn) p.draw_sweeps = 500;
+            all_drawn = all_drawn && drawn;
+        }
+        if (all_drawn) p.sweeps_per_graph = 500;
     }
     int rc = apply_plan(b, p);
     if (rc != ISING_OK) {
@@ -596,7 +673,7 @@ std::string cache_key(const ising_batch* b) {
     std::map<int32_t, int32_t> hist;
     for (const auto& g : b->geo) hist[g.L] += 1;
     std::ostringstream os;
-    os << b->arch << "|plan3|";
+    os << b->arch << "|plan4|";
     bool first = true;
     for (auto& kv : hist) {
         os << (first ? "" : ",") << kv.first << "x" << kv.second;
@@ -618,9 +695,10 @@ bool cache_lookup(const char* path, const std::string& key, ising_batch_plan* p)
         if (std::sscanf(line.c_str() + at + want.size(),
                         " {\"resident_max_L\": %d, \"resident_block\": %d, \"words_per_thread\": %d, \"tiled_block\": %d, "
                         "\"sweeps_per_graph\": %d, \"tile_max_L\": %d, \"tile_sweeps\": %d, \"tile_cols\": %d, "
-                        "\"tile_block\": %d, \"tile_exchange\": %d",
+                        "\"tile_block\": %d, \"tile_exchange\": %d, \"draw_sweeps\": %d",
                         &q.resident_max_L, &q.resident_block, &q.words_per_thread, &q.tiled_block, &q.sweeps_per_graph,
-                        &q.tile_max_L, &q.tile_sweeps, &q.tile_cols, &q.tile_block, &q.tile_exchange) == 10) {
+                        &q.tile_max_L, &q.tile_sweeps, &q.tile_cols, &q.tile_block, &q.tile_exchange,
+                        &q.draw_sweeps) == 11) {
             *p = q;
             return true;
         }
@@ -645,9 +723,9 @@ void cache_store(const char* path, const std::string& key, const ising_batch_pla
     std::snprintf(buf, sizeof buf,
                   "\"%s\": {\"resident_max_L\": %d, \"resident_block\": %d, \"words_per_thread\": %d, \"tiled_block\": "
                   "%d, \"sweeps_per_graph\": %d, \"tile_max_L\": %d, \"tile_sweeps\": %d, \"tile_cols\": %d, "
-                  "\"tile_block\": %d, \"tile_exchange\": %d, \"ms_per_sweep\": %.6f}",
+                  "\"tile_block\": %d, \"tile_exchange\": %d, \"draw_sweeps\": %d, \"ms_per_sweep\": %.6f}",
                   key.c_str(), p.resident_max_L, p.resident_block, p.words_per_thread, p.tiled_block, p.sweeps_per_graph,
-                  p.tile_max_L, p.tile_sweeps, p.tile_cols, p.tile_block, p.tile_exchange, ms);
+                  p.tile_max_L, p.tile_sweeps, p.tile_cols, p.tile_block, p.tile_exchange, p.draw_sweeps, ms);
     lines.push_back(buf);
     std::ofstream f(path, std::ios::trunc);
     f << "{\n";
@@ -933,9 +1011,30 @@ int ising_batch_autotune(ising_batch* b, const double* T, const char* cache_path
             p.resident_block = rb;
             rc = consider(p);
         }
+    // 2b) the smallest lattices with their codes drawn chip-wide
+    {
+        const ising_batch_plan res_best = best;
+        int32_t Ld = 0;
+        for (int32_t L0 : distinct) {
+            const Geometry g = make_geometry(L0);
+            if (wave_apply_words_per_thread(g.L, g.N, 256) > 0 && wave_apply_lds_bytes(g.N * g.L, 1000) <= lds_limit)
+                Ld = L0;
+        }
+        if (Ld > 0)
+            for (int rb : {64, 128, 256})
+                for (int ds : {100, 1000}) {
+                    if (rc != ISING_OK) break;
+                    ising_batch_plan p = res_best;
+                    p.resident_max_L = std::max(res_best.resident_max_L, Ld);
+                    p.resident_block = rb;
+                    p.draw_sweeps = ds;
+                    p.sweeps_per_graph = std::min(sweeps, 1000);
+                    rc = consider(p);
+                }
+    }
     // 3) sweeps per graph
     const ising_batch_plan shape_best = best;
-    for (int k : {10, 50, 100, 250}) {
+    for (int k : {10, 50, 100, 250, 1000}) {
         if (rc != ISING_OK) break;
         ising_batch_plan p = shape_best;
         p.sweeps_per_graph = std::min(k, sweeps);

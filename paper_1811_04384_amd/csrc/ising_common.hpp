@@ -179,4 +179,14 @@ struct PersistLaunch {
     uint64_t wait_ticks;
 };
 
+// A small lattice whose acceptance codes are drawn ahead by a chip-wide
+// launch into a global buffer: its codes of sweep j of a draw pass start at
+// codes + base + j N L (layout [sweeps][N][L]); n_draw = 2 N ceil(L / 8)
+// draw items per sweep (colour, word row, 8-column group).
+struct DrawLat {
+    int32_t lat;
+    int32_t n_draw;
+    int64_t base;
+};
+
 }  // namespace ising

@@ -176,6 +176,27 @@ hipError_t allow_small_lds(int device);
 hipError_t launch_small(int block, const LatticeDesc* descs, LatticeState* states, const int32_t* ids, int32_t n_ids,
                         int32_t K, int32_t every, int32_t batch, size_t lds_bytes, hipStream_t s);
 
+// ---- small lattices with their draws spread over the chip --------------------
+
+// Draw pass: the acceptance codes of sweeps [sweep_off, sweep_off + S) of
+// the current chunk of each listed lattice into codes (DrawLat layout);
+// max_n_draw = the largest n_draw of the list.
+hipError_t launch_draw_codes(const LatticeDesc* descs, const LatticeState* states, const DrawLat* lats, int32_t n_lats,
+                             int32_t max_n_draw, uint64_t* codes, int32_t sweep_off, int32_t S, hipStream_t s);
+// Apply pass over the same sweeps: one workgroup of `block` threads (64,
+// 128 or 256) per listed lattice, wmax (1, 2 or 4:
+// wave_apply_words_per_thread) words of a colour per thread, codes loaded
+// from the buffer into registers ahead of use; lds_bytes =
+// wave_apply_lds_bytes(largest N L, S).  Samples as launch_resident.
+hipError_t launch_wave_apply(int wmax, int block, const LatticeDesc* descs, LatticeState* states, const DrawLat* lats,
+                             int32_t n_lats, const uint64_t* codes, int32_t sweep_off, int32_t S, int32_t every,
+                             size_t lds_bytes, hipStream_t s);
+size_t wave_apply_lds_bytes(int32_t NL, int32_t max_samples);
+// Words of one colour per thread of a `block`-thread apply workgroup (0:
+// more than 4).
+int32_t wave_apply_words_per_thread(int32_t L, int32_t N, int32_t block);
+hipError_t allow_wave_apply_lds(int device);
+
 // Largest dynamic LDS a resident workgroup may use on this device.
 size_t resident_lds_limit(int device);
 

@@ -43,4 +43,39 @@ __device__ inline void add_sample(Moments& m, int64_t E, int64_t M) {
     m.sum_M4[2] += l2 + (uint64_t)(b >> 64);
 }
 
+// a += b, exactly (limb sums with carries; the sums are integers, so the
+// order in which samples are merged does not matter).
+__device__ inline void merge_moments(Moments& a, const Moments& b) {
+    typedef unsigned __int128 u128;
+    a.n += b.n;
+    a.sum_E += b.sum_E;
+    a.sum_absM += b.sum_absM;
+    add128(a.sum_E2, ((u128)b.sum_E2[1] << 64) | b.sum_E2[0]);
+    add128(a.sum_M2, ((u128)b.sum_M2[1] << 64) | b.sum_M2[0]);
+    const u128 x = (u128)a.sum_M4[0] + b.sum_M4[0];
+    const u128 y = (u128)a.sum_M4[1] + b.sum_M4[1] + (uint64_t)(x >> 64);
+    a.sum_M4[0] = (uint64_t)x;
+    a.sum_M4[1] = (uint64_t)y;
+    a.sum_M4[2] += b.sum_M4[2] + (uint64_t)(y >> 64);
+}
+
+// Every lane of a full wavefront ends with the merge of all 64 lanes' sums.
+__device__ inline void wave_merge_moments(Moments& m) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        Moments o;
+        o.n = __shfl_xor(m.n, off, 64);
+        o.sum_E = __shfl_xor(m.sum_E, off, 64);
+        o.sum_absM = __shfl_xor(m.sum_absM, off, 64);
+        o.sum_E2[0] = __shfl_xor(m.sum_E2[0], off, 64);
+        o.sum_E2[1] = __shfl_xor(m.sum_E2[1], off, 64);
+        o.sum_M2[0] = __shfl_xor(m.sum_M2[0], off, 64);
+        o.sum_M2[1] = __shfl_xor(m.sum_M2[1], off, 64);
+        o.sum_M4[0] = __shfl_xor(m.sum_M4[0], off, 64);
+        o.sum_M4[1] = __shfl_xor(m.sum_M4[1], off, 64);
+        o.sum_M4[2] = __shfl_xor(m.sum_M4[2], off, 64);
+        merge_moments(m, o);
+    }
+}
+
 }  // namespace ising

@@ -135,9 +135,10 @@ def test_batch_plan_check_bounds_resident_lattices():
     # bits), before any batch or GPU exists
     ok = dict(resident_max_L=4096, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=50)
     ising.ising_batch_check_plan(ok)
+    ising.ising_batch_check_plan(dict(ok, draw_sweeps=4096))
     for bad in (dict(ok, resident_max_L=1 << 18), dict(ok, resident_max_L=4098), dict(ok, resident_max_L=-2),
                 dict(ok, words_per_thread=3), dict(ok, tiled_block=96), dict(ok, resident_block=2048),
-                dict(ok, sweeps_per_graph=0)):
+                dict(ok, sweeps_per_graph=0), dict(ok, draw_sweeps=-1), dict(ok, draw_sweeps=4097)):
         with pytest.raises(ising.IsingError) as e:
             ising.ising_batch_check_plan(bad)
         assert e.value.code == ising.ISING_EINVAL

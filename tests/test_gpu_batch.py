@@ -1,8 +1,8 @@
 """GPU parity of the batched form: every lattice of a mixed batch equals the
 oracle (and therefore the same lattice run alone), for every execution plan
 (resident in LDS, resident in global memory, half-sweep launches with 1/2/4
-words per thread, multi-sweep LDS tiles, several chunk lengths), including
-sample series and sums."""
+words per thread, multi-sweep LDS tiles, resident tiles, codes drawn
+chip-wide, several chunk lengths), including sample series and sums."""
 import numpy as np
 import pytest
 
@@ -57,6 +57,16 @@ PLANS = [
     # resident lattices, resident tiles (two-column bands) and half-sweep launches in one chunk
     dict(resident_max_L=64, resident_block=256, words_per_thread=2, tiled_block=128, sweeps_per_graph=6,
          tile_max_L=512, tile_sweeps=1, tile_cols=2, tile_block=64, tile_exchange=1),
+    # codes drawn chip-wide for L <= 128 (draw passes of 4 + 3 sweeps), one
+    # wavefront per apply workgroup (up to 8 words of a colour per thread
+    # is too many for L = 128: it stays on k_small); the rest on half-sweep
+    # launches
+    dict(resident_max_L=128, resident_block=64, words_per_thread=1, tiled_block=64, sweeps_per_graph=7,
+         draw_sweeps=4),
+    # the same with four wavefronts per apply workgroup, beside k_small
+    # (L = 256), resident tiles and half-sweep launches
+    dict(resident_max_L=256, resident_block=256, words_per_thread=2, tiled_block=128, sweeps_per_graph=6,
+         tile_max_L=512, tile_sweeps=1, tile_cols=32, tile_block=256, tile_exchange=1, draw_sweeps=3),
 ]
 
 
@@ -78,6 +88,55 @@ def test_batch_matches_oracle(plan):
             assert res["n_samples"][i] == n2 // every
             assert res["sum_E"][i] == Es.sum() and res["sum_absM"][i] == np.abs(Ms).sum()
             assert b.sweep_count(i) == n1 + n2
+    finally:
+        b.close()
+
+
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_drawn_codes_across_passes(block):
+    """Codes drawn chip-wide: 40 sweeps per chunk in draw passes of 30 + 10
+    (the apply kernel's codes run several sweeps ahead of their use, across
+    its unrolled steps and the pass ends), samples every third sweep; then a
+    second call that starts mid-way through the counter, sampling every
+    sweep.  With 64 threads L = 128 has too many words per thread and stays
+    on the in-workgroup path."""
+    Ls, seeds, Ts = [128, 64, 84, 6, 4], [21, 22, 23, 24, 25], [2.0, 2.3, 2.6, 3.0, 1.7]
+    b = ising.Batch(Ls, seeds, hot=True)
+    try:
+        b.set_plan(resident_max_L=128, resident_block=block, words_per_thread=1, tiled_block=64, sweeps_per_graph=40,
+                   draw_sweeps=30)
+        E1, M1 = b.sweep(Ts, 40, every=3, series=True)
+        E2, M2 = b.sweep(Ts, 17, every=1, series=True)
+        E1, M1, E2, M2 = (x.cpu().numpy() for x in (E1, M1, E2, M2))
+        for i, (L, seed, T) in enumerate(zip(Ls, seeds, Ts)):
+            s = oracle.init(L, seed, True)
+            Es1, Ms1 = oracle.sweep(s, seed, 0, 40, T, every=3)
+            Es2, Ms2 = oracle.sweep(s, seed, 40, 17, T, every=1)
+            assert E1[i].tolist() == Es1.tolist() and M1[i].tolist() == Ms1.tolist(), (i, L)
+            assert E2[i].tolist() == Es2.tolist() and M2[i].tolist() == Ms2.tolist(), (i, L)
+            assert (b.spins(i) == s).all(), (i, L)
+    finally:
+        b.close()
+
+
+def test_drawn_codes_many_lattices():
+    """More lattices than compute units: the apply workgroups share compute
+    units with smaller LDS code buffers."""
+    n = 300
+    Ls = [(4, 6, 8, 10)[i % 4] for i in range(n)]
+    seeds = list(range(100, 100 + n))
+    Ts = [1.5 + 2.0 * (i % 11) / 10 for i in range(n)]
+    b = ising.Batch(Ls, seeds, hot=True)
+    try:
+        b.set_plan(resident_max_L=10, resident_block=64, words_per_thread=1, tiled_block=64, sweeps_per_graph=25,
+                   draw_sweeps=25)
+        E, M = b.sweep(Ts, 25, every=5, series=True)
+        E, M = E.cpu().numpy(), M.cpu().numpy()
+        for i in range(0, n, 7):
+            s = oracle.init(Ls[i], seeds[i], True)
+            Es, Ms = oracle.sweep(s, seeds[i], 0, 25, Ts[i], every=5)
+            assert E[i].tolist() == Es.tolist() and M[i].tolist() == Ms.tolist(), i
+            assert (b.spins(i) == s).all(), i
     finally:
         b.close()
 

@@ -88,10 +88,13 @@ PLANS = [
          tile_max_L=1008, tile_sweeps=2, tile_cols=16, tile_block=256),
     dict(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=6,
          tile_max_L=1008, tile_sweeps=1, tile_cols=16, tile_block=256, tile_exchange=1),
+    dict(resident_max_L=130, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=6,
+         draw_sweeps=4),
 ]
 
 
-@pytest.mark.parametrize("plan", PLANS, ids=["tiled", "resident_lds", "resident_all", "lds_tiles", "resident_tiles"])
+@pytest.mark.parametrize("plan", PLANS, ids=["tiled", "resident_lds", "resident_all", "lds_tiles", "resident_tiles",
+                                             "drawn_codes"])
 def test_batch_scan_matches_oracle(plan):
     print(f"batch scan plan={plan}", flush=True)
     n = len(BATCH_LS)

@@ -36,11 +36,13 @@ def _gpu():
     ising.load()
 
 
-def test_scan_l64_full_run_matches_oracle():
+@pytest.mark.parametrize("draw_sweeps", [0, 500], ids=["in_workgroup", "drawn_chip_wide"])
+def test_scan_l64_full_run_matches_oracle(draw_sweeps):
     Ts = [1.5 + 2.0 * i / 7 for i in range(8)]
     b = ising.Batch([64] * 8, [1234] * 8, hot=False)
     try:
-        b.set_plan(resident_max_L=64, resident_block=64, words_per_thread=1, tiled_block=256, sweeps_per_graph=500)
+        b.set_plan(resident_max_L=64, resident_block=64 if draw_sweeps == 0 else 256, words_per_thread=1,
+                   tiled_block=256, sweeps_per_graph=500, draw_sweeps=draw_sweeps)
         b.sweep(Ts, 2000)
         E, M = b.sweep(Ts, 2000, every=1, series=True)
         E, M = E.cpu().numpy(), M.cpu().numpy()
