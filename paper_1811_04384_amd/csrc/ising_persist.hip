@@ -337,13 +337,18 @@ __global__ void __launch_bounds__(256) k_samples_em(const Partial* __restrict__ 
     }
 }
 
-// Moment sums of n samples, added in order by one thread.
-__global__ void k_samples_moments(const int64_t* __restrict__ E, const int64_t* __restrict__ M, int32_t n,
-                                  Moments* mom) {
-    if (threadIdx.x != 0) return;
-    Moments m = *mom;
-    for (int k = 0; k < n; ++k) add_sample(m, E[k], M[k]);
-    *mom = m;
+// Moment sums of n samples added to *mom, by one wavefront: per-lane sums
+// of samples l, l + 64, ..., merged exactly.
+__global__ void __launch_bounds__(64) k_samples_moments(const int64_t* __restrict__ E, const int64_t* __restrict__ M,
+                                                        int32_t n, Moments* mom) {
+    Moments part = {};
+    for (int k = lane_id(); k < n; k += 64) add_sample(part, E[k], M[k]);
+    wave_merge_moments(part);
+    if (lane_id() == 0) {
+        Moments m = *mom;
+        merge_moments(m, part);
+        *mom = m;
+    }
 }
 
 }  // namespace
@@ -351,48 +356,49 @@ __global__ void k_samples_moments(const int64_t* __restrict__ E, const int64_t* 
 namespace {
 
 // The samples of one launch of resident tiles for every tiled lattice of a
-// batch, one wavefront per listed lattice: lane l takes sample base + l (the
-// sum of the lattice's tile partials), then lane 0 adds them in order to the
-// moment sums and the last E, M.
+// batch, one wavefront per listed lattice: lane l takes samples l, l + 64,
+// ... (the sum of the lattice's tile partials), writes their E, M to the
+// series and adds them to its own moment sums; the lanes' sums are then
+// merged exactly, and lane 0 adds them to the lattice's with the last E, M.
 __global__ void __launch_bounds__(64) k_finalize_resident(const LatticeDesc* __restrict__ descs,
                                                           LatticeState* __restrict__ states,
                                                           const int32_t* __restrict__ ids,
                                                           const Partial* __restrict__ partials, int32_t n_tiles,
                                                           int32_t n_samples) {
-    __shared__ int64_t sE[64], sM[64];
     const int32_t lat = ids[blockIdx.x];
     const LatticeDesc& d = descs[lat];
     LatticeState& st = states[lat];
     const int n = min(n_samples, d.sweep_limit);  // a lattice past its limit took fewer samples
+    if (n <= 0) return;
     const int64_t spins = (int64_t)d.L * (int64_t)d.L;
     const int64_t idx = st.series_idx;
-    for (int base = 0; base < n; base += 64) {
-        const int o = base + lane_id();
-        if (o < n) {
-            unsigned long long anti = 0, ups = 0;
-            const Partial* __restrict__ part = partials + (size_t)o * n_tiles + d.part_begin;
-            for (int i = 0; i < d.part_count; ++i) {
-                anti += part[i].anti;
-                ups += part[i].ups;
-            }
-            const int64_t E = 2 * (int64_t)anti - 2 * spins, M = 2 * (int64_t)ups - spins;
-            sE[lane_id()] = E;
-            sM[lane_id()] = M;
-            if (d.series_E) d.series_E[idx + o] = E;
-            if (d.series_M) d.series_M[idx + o] = M;
+    Moments part = {};
+    int64_t E = 0, M = 0;
+    for (int o = lane_id(); o < n; o += 64) {
+        unsigned long long anti = 0, ups = 0;
+        const Partial* __restrict__ p = partials + (size_t)o * n_tiles + d.part_begin;
+        for (int i = 0; i < d.part_count; ++i) {
+            anti += p[i].anti;
+            ups += p[i].ups;
         }
-        __syncthreads();
-        if (lane_id() == 0) {
-            Moments m = st.mom;
-            const int cnt = min(64, n - base);
-            for (int k = 0; k < cnt; ++k) add_sample(m, sE[k], sM[k]);
-            st.mom = m;
-            st.last_E = sE[cnt - 1];
-            st.last_M = sM[cnt - 1];
-        }
-        __syncthreads();
+        E = 2 * (int64_t)anti - 2 * spins;
+        M = 2 * (int64_t)ups - spins;
+        if (d.series_E) d.series_E[idx + o] = E;
+        if (d.series_M) d.series_M[idx + o] = M;
+        add_sample(part, E, M);
     }
-    if (lane_id() == 0) st.series_idx = idx + n;
+    wave_merge_moments(part);
+    // the lane that took the last sample holds its E, M
+    const int last = (n - 1) & 63;
+    const int64_t lE = __shfl(E, last, 64), lM = __shfl(M, last, 64);
+    if (lane_id() == 0) {
+        Moments m = st.mom;
+        merge_moments(m, part);
+        st.mom = m;
+        st.last_E = lE;
+        st.last_M = lM;
+        st.series_idx = idx + n;
+    }
 }
 
 }  // namespace
