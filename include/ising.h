@@ -295,6 +295,16 @@ int ising_get_tiling(ising_lattice* h, int32_t* sweeps_per_launch, int32_t* tile
    (bands of 2 ceil(L / 512) columns, 1024 threads, 1000 sweeps per launch)
    when those fit. */
 int ising_set_resident_tiles(ising_lattice* h, int32_t tile_cols, int32_t block, int32_t max_sweeps);
+/* Bound of every wait of the resident-tile launches for their neighbour
+   tiles, in ticks of the GPU's 100 MHz constant clock; 0 restores the
+   default of 100,000,000 (one second), at most one minute (EINVAL beyond).
+   A launch whose wait runs past it sets an error word and every tile of the
+   launch stops at once, so the launch always ends; the next call on the
+   handle that checks (a sweep, ising_observables, ising_synchronize)
+   returns ISING_EHIP and clears it, and the lattice state is undefined until
+   ising_reset or ising_set_spins.  A small bound is how a caller (a test)
+   can exercise that path without a fault. */
+int ising_set_resident_wait(ising_lattice* h, uint64_t ticks);
 int ising_get_resident_tiles(ising_lattice* h, int32_t* tile_cols, int32_t* block, int32_t* max_sweeps);
 
 /* Time every plan on this lattice's shape (on a scratch copy, the state is

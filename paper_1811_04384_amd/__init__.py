@@ -282,6 +282,10 @@ def ising_set_resident_tiles(h, tile_cols, block=512, max_sweeps=1000):
     _check(_lib.load().ising_set_resident_tiles(h, int(tile_cols), int(block), int(max_sweeps)))
 
 
+def ising_set_resident_wait(h, ticks):
+    _check(_lib.load().ising_set_resident_wait(h, int(ticks)))
+
+
 def ising_get_resident_tiles(h):
     c, b, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(_lib.load().ising_get_resident_tiles(h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(k)))
@@ -589,6 +593,9 @@ class Lattice:
 
     def resident_tiles(self):
         return ising_get_resident_tiles(self.handle)
+
+    def set_resident_wait(self, ticks):
+        ising_set_resident_wait(self.handle, ticks)
 
     def autotune(self, T):
         return ising_autotune(self.handle, T)

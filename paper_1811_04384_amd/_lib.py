@@ -75,6 +75,7 @@ SIGNATURES = {
     "ising_get_tiling": (c_int, [c_vp, P(c_i32), P(c_i32), P(c_i32)]),
     "ising_set_resident_tiles": (c_int, [c_vp, c_i32, c_i32, c_i32]),
     "ising_get_resident_tiles": (c_int, [c_vp, P(c_i32), P(c_i32), P(c_i32)]),
+    "ising_set_resident_wait": (c_int, [c_vp, ctypes.c_uint64]),
     "ising_sweep_measure_static": (c_int, [c_vp, c_sz, c_i32, c_u64, c_u64, c_dbl, c_i64, c_i32, c_vp, c_vp, c_vp]),
     "ising_set_plan": (c_int, [c_vp, c_i32, c_i32]),
     "ising_get_plan": (c_int, [c_vp, P(c_i32), P(c_i32)]),

@@ -44,8 +44,9 @@ struct ising_lattice {
     PersistTile* d_res = nullptr;
     uint64_t* d_exch = nullptr;
     uint64_t* d_flags = nullptr;
-    uint32_t* d_err = nullptr;
+    uint32_t* d_err = nullptr;      // 8 bytes: the error word and padding, cleared by a kernel
     uint32_t* h_err = nullptr;      // pinned copy of d_err, refreshed after every launch
+    uint64_t res_wait = 0;          // bound of each wait, 100 MHz clock ticks
     Partial* d_rpart = nullptr;     // res_sweeps x n_res partial sums
     int64_t* d_rEM = nullptr;       // 2 x res_sweeps sample scratch (moments without a series)
 };
@@ -311,10 +312,13 @@ static int enqueue_tile_sweeps(const ising_lattice* h, uint64_t t0, double T, in
 constexpr uint64_t kResidentWaitTicks = 100000000ull;
 
 // Error left by an earlier resident-tile launch (its copy lands in pinned
-// memory behind the launch); cleared once reported.
-static int resident_error(const ising_lattice* h) {
+// memory behind the launch); cleared once reported, the device word by a
+// kernel on the handle's stream (ahead of any later launch, and valid under
+// graph capture).
+static int resident_error(ising_lattice* h) {
     if (h->h_err && *(volatile uint32_t*)h->h_err) {
         *(volatile uint32_t*)h->h_err = 0;
+        ISING_HIP(launch_zero_words(reinterpret_cast<uint64_t*>(h->d_err), 1, h->stream));
         return fail(ISING_EHIP, "resident tiles: a launch waited too long for its neighbour tiles and was abandoned; "
                                 "the lattice state is undefined");
     }
@@ -338,7 +342,7 @@ static int enqueue_resident_sweeps(ising_lattice* h, uint64_t t0, double T, int6
     a.exch_tile_words = 4 * (int64_t)h->g.N;
     a.flags = h->d_flags;
     a.error = h->d_err;
-    a.wait_ticks = kResidentWaitTicks;
+    a.wait_ticks = h->res_wait ? h->res_wait : kResidentWaitTicks;
     for (int64_t done = 0; done < n;) {
         const int32_t kb = (int32_t)std::min<int64_t>(h->res_sweeps, n - done);
         a.t0 = t0 + (uint64_t)done;
@@ -749,8 +753,8 @@ int ising_set_resident_tiles(ising_lattice* h, int32_t tile_cols, int32_t block,
     if (e == hipSuccess) e = hipMalloc(&h->d_exch, sizeof(uint64_t) * 4 * (size_t)N * n);
     if (e == hipSuccess) e = hipMalloc(&h->d_flags, sizeof(uint64_t) * n);
     if (e == hipSuccess) e = hipMemset(h->d_flags, 0, sizeof(uint64_t) * n);
-    if (e == hipSuccess && !h->d_err) e = hipMalloc(&h->d_err, sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(h->d_err, 0, sizeof(uint32_t));
+    if (e == hipSuccess && !h->d_err) e = hipMalloc(&h->d_err, sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemset(h->d_err, 0, sizeof(uint64_t));
     if (e == hipSuccess && !h->h_err) e = hipHostMalloc(&h->h_err, sizeof(uint32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc(&h->d_rpart, sizeof(Partial) * (size_t)max_sweeps * n);
     if (e == hipSuccess) e = hipMalloc(&h->d_rEM, sizeof(int64_t) * 2 * (size_t)max_sweeps);
@@ -764,6 +768,15 @@ int ising_set_resident_tiles(ising_lattice* h, int32_t tile_cols, int32_t block,
     h->res_block = block;
     h->res_sweeps = max_sweeps;
     h->res_lds = lds;
+    return ISING_OK;
+}
+
+int ising_set_resident_wait(ising_lattice* h, uint64_t ticks) {
+    if (!h) return fail(ISING_EINVAL, "ising_set_resident_wait: null handle");
+    if (ticks > kResidentWaitTicks * 60)
+        return fail(ISING_EINVAL, "ising_set_resident_wait: at most %llu ticks (one minute)",
+                    (unsigned long long)(kResidentWaitTicks * 60));
+    h->res_wait = ticks;  // 0: the default
     return ISING_OK;
 }
 

@@ -160,3 +160,33 @@ def test_resident_tiles_after_reset_and_counter_set_back():
         assert (lat.spins() == s).all() and lat.t == 9
     finally:
         lat.close()
+
+
+def test_resident_tiles_expired_wait_is_reported_and_recoverable():
+    """Failure path forced from the host: with the bound of every wait set to
+    one tick (10 ns) the tiles' waits for their neighbours expire, the
+    launches stop early (every wait is bounded, so they end), the error is
+    reported once as ISING_EHIP, and after ising_reset with the default bound
+    the lattice runs as the oracle again."""
+    L, seed, T = 4096, 7, 2.269
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        assert lat.resident_tiles()[0] > 0
+        lat.set_resident_wait(1)
+        print("resident tiles with a one-tick wait bound", flush=True)
+        lat.sweep(T, 40)
+        with pytest.raises(ising.IsingError) as e:
+            lat.synchronize()
+        assert e.value.code == ising.ISING_EHIP and "waited too long" in ising.ising_last_error()
+        lat.synchronize()  # reported once
+        lat.set_resident_wait(0)
+        lat.reset(seed, hot=True)
+        E, M = lat.sweep_measure(T, 20, 10)
+        got = lat.spins()
+        got_E, got_M = E.cpu().numpy().tolist(), M.cpu().numpy().tolist()
+    finally:
+        lat.close()
+    s = oracle.init(L, seed, True)
+    Es, Ms = oracle.sweep(s, seed, 0, 20, T, every=10)
+    assert got_E == Es.tolist() and got_M == Ms.tolist()
+    assert (got == s).all()
