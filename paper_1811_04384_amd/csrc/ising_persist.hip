@@ -166,13 +166,11 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
         const uint64_t* __restrict__ gr = a.exch + (size_t)tp.right * tw + (size_t)(1 - c) * 2 * N;      // its left side
         uint64_t* __restrict__ ex = a.exch + (size_t)blockIdx.x * tw + (size_t)c * 2 * N;
         uint32_t anti = 0, ups = 0;
-        for (int f = tid; f < n_b + n_i + n_u; f += B) {
-            if (f >= n_b + n_i) {  // the next half-sweep's position-20 blocks
-                int I, k;
-                divmod_small(f - n_b - n_i, n_groups, rcp_g, I, k);
-                if (pstar + (I <= istar ? 1 : 0) == 21) u5next[(size_t)k * N + I] = block5(sw_next, rk, I, g_lo + k, c ^ 1);
-                continue;
-            }
+        // items f = tid, tid + B, ...: the words (boundary, then interior),
+        // then the next half-sweep's position-20 blocks, in two loops so that
+        // each keeps only its own wave-uniform values live
+        int f = tid;
+        for (; f < n_b + n_i; f += B) {
             int I, x, side = -1;
             if (f < n_b) {  // items f < N/2: column 1 (left side), the others column w (right side)
                 side = f >= (N >> 1) ? 1 : 0;
@@ -192,7 +190,14 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
                 if (x == w) nb.rt = __hip_atomic_load(&gr[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             const uint32_t u20 = pick4(u5cur[(size_t)((J >> 3) - g_lo) * N + I], ((uint32_t)J >> 1) & 3u);
-            const uint64_t nw = lds_word_update(sw, rk, nb, I, J, u20, meas, true, anti, ups);
+            // the sweep index made opaque to the compiler here, so that the
+            // wave-uniform parts of the Philox rounds are formed per item on
+            // the scalar unit instead of being hoisted out of the loop for
+            // all five blocks (which overflows the scalar registers into
+            // vector-lane spills)
+            LdsSweep swi = sw;
+            asm volatile("" : "+s"(swi.t_lo), "+s"(swi.t_hi));
+            const uint64_t nw = lds_word_update(swi, rk, nb, I, J, u20, meas, true, anti, ups);
             T[I * width + x] = nw;
             if (side >= 0) {
                 // publish; the last of the N boundary words raises the flag
@@ -205,6 +210,11 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
                     __hip_atomic_store(&a.flags[blockIdx.x], 2 * t0 + (uint64_t)hs + 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
+        }
+        for (; f < n_b + n_i + n_u; f += B) {
+            int I, k;
+            divmod_small(f - n_b - n_i, n_groups, rcp_g, I, k);
+            if (pstar + (I <= istar ? 1 : 0) == 21) u5next[(size_t)k * N + I] = block5(sw_next, rk, I, g_lo + k, c ^ 1);
         }
         if (meas) {
             anti = wave_sum_u32(anti);
