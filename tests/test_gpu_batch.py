@@ -119,6 +119,33 @@ def test_drawn_codes_across_passes(block):
         b.close()
 
 
+def test_drawn_codes_small_shapes():
+    """Codes drawn chip-wide for the small shapes: two and four word rows,
+    the row-(L-1) patch in either word row, L = 4 ... 84 in one batch;
+    samples every second sweep over a pass boundary, then every sweep."""
+    Ls = [4, 6, 20, 22, 42, 44, 62, 64, 84]
+    seeds = list(range(60, 60 + len(Ls)))
+    Ts = [1.6 + 0.2 * i for i in range(len(Ls))]
+    b = ising.Batch(Ls, seeds, hot=True)
+    try:
+        b.set_plan(resident_max_L=84, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=30,
+                   draw_sweeps=12)
+        E1, M1 = b.sweep(Ts, 30, every=2, series=True)
+        E2, M2 = b.sweep(Ts, 11, every=1, series=True)
+        E1, M1, E2, M2 = (x.cpu().numpy() for x in (E1, M1, E2, M2))
+        res = b.results()
+        for i, (L, seed, T) in enumerate(zip(Ls, seeds, Ts)):
+            s = oracle.init(L, seed, True)
+            Es1, Ms1 = oracle.sweep(s, seed, 0, 30, T, every=2)
+            Es2, Ms2 = oracle.sweep(s, seed, 30, 11, T, every=1)
+            assert E1[i].tolist() == Es1.tolist() and M1[i].tolist() == Ms1.tolist(), (i, L)
+            assert E2[i].tolist() == Es2.tolist() and M2[i].tolist() == Ms2.tolist(), (i, L)
+            assert (b.spins(i) == s).all(), (i, L)
+            assert (res["E"][i], res["M"][i]) == oracle.observables(s)
+    finally:
+        b.close()
+
+
 def test_drawn_codes_many_lattices():
     """More lattices than compute units: the apply workgroups share compute
     units with smaller LDS code buffers."""
