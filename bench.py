@@ -241,7 +241,7 @@ def cpu_baseline(target_s=12.0, single_s=4.0):
 # secondary workloads
 # ---------------------------------------------------------------------------
 
-def run_plain4096(ising, sweeps=10000, every=10):
+def run_plain4096(ising, sweeps=10000, every=10, plain=True):
     """Single lattice L=4096, hot start seed 7, T=2.269, E/M every 10 sweeps,
     one lattice per launch (the plain form), in the library's default plan
     for this size (resident tiles: 256 bands of 16 word columns kept in LDS
@@ -268,12 +268,14 @@ def run_plain4096(ising, sweeps=10000, every=10):
         return ms, e, plan
 
     ms, e, plan = timed(True)
-    ms_h, e_h, _ = timed(False)
-    assert e == e_h, "the two plans must give the same series"
-    return {"workload": "L=4096 single, hot seed 7, T=2.269, 10000 sweeps, E/M every 10",
-            "value": round(4096 ** 2 * sweeps / (ms * 1e6), 2), "unit": UNIT, "ms": round(ms, 2),
-            "plan": plan, "mean_e_per_spin": round(e, 6),
-            "half_sweep_launches": {"value": round(4096 ** 2 * sweeps / (ms_h * 1e6), 2), "ms": round(ms_h, 2)}}
+    out = {"workload": "L=4096 single, hot seed 7, T=2.269, 10000 sweeps, E/M every 10",
+           "value": round(4096 ** 2 * sweeps / (ms * 1e6), 2), "unit": UNIT, "ms": round(ms, 2),
+           "plan": plan, "mean_e_per_spin": round(e, 6)}
+    if plain:
+        ms_h, e_h, _ = timed(False)
+        assert e == e_h, "the two plans must give the same series"
+        out["half_sweep_launches"] = {"value": round(4096 ** 2 * sweeps / (ms_h * 1e6), 2), "ms": round(ms_h, 2)}
+    return out
 
 
 def run_graph4096(ising, sweeps=10000, every=10):
@@ -473,7 +475,7 @@ def run_paper_scan(ising, L=84, replicas=8, iterations=400, per_iteration=10):
             "T_every_5th": [round(T, 3) for T in Ts[::5]], "mean_e_per_spin_every_5th": [round(e, 4) for e in e_T[::5]]}
 
 
-def run_paper_cases(ising, strip_cols=2, T=2.269):
+def run_paper_cases(ising, strip_cols=2, T=2.269, iterations=None):
     """The paper's three test cases (Table 2) with its own dynamics: random
     word picks inside strips of `strip_cols` word columns (L / strip_cols
     processes, each a GPU thread), left half then right half per iteration,
@@ -486,6 +488,7 @@ def run_paper_cases(ising, strip_cols=2, T=2.269):
 
     out = {}
     for case, (L, iters) in enumerate(((2016, 5000), (2016, 4500), (1008, 4500)), start=1):
+        iters = iterations or iters
         lat = ising.Lattice(L, case, hot=True)
         acc = torch.zeros(10, dtype=torch.int64, device="cuda")
         torch.cuda.synchronize()
@@ -616,7 +619,7 @@ def run_serving_bounded(ising, rates=(25.0, 50.0, 75.0), duration=10.0, quantum=
 
 def run_secondary(ising, name, args):
     if name == "plain4096":
-        return run_plain4096(ising)
+        return run_plain4096(ising, plain=not args.no_plain)
     if name == "graph4096":
         return run_graph4096(ising)
     if name == "batched":
@@ -628,7 +631,7 @@ def run_secondary(ising, name, args):
     if name == "paper_scan":
         return run_paper_scan(ising)
     if name == "paper_cases":
-        return run_paper_cases(ising)
+        return run_paper_cases(ising, iterations=args.paper_iterations)
     if name == "replicas":
         return run_replicas(ising)
     if name == "serving_bounded":
@@ -668,9 +671,12 @@ def main():
                          "print one JSON line with their results (for profiling one kernel at a time)")
     ap.add_argument("--batched-sweeps", type=int, default=5000,
                     help="sweeps of the batched mix (5000 as specified; fewer for a profiling run)")
+    ap.add_argument("--paper-iterations", type=int, default=None, metavar="N",
+                    help="run each of the paper's Table 2 cases for N iterations instead of its own count "
+                         "(for counter runs)")
     ap.add_argument("--no-plain", action="store_true",
-                    help="skip the one-lattice-per-launch comparisons of the batched mix and the L = 64 scan "
-                         "(tens of thousands of short launches; for counter runs)")
+                    help="skip the one-launch-per-half-sweep comparisons of the L = 4096 lattice, the batched "
+                         "mix and the L = 64 scan (tens of thousands of short launches; for counter runs)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run the batched mix in its default plan instead of the autotuned one")
     ap.add_argument("--build-valu-rates", action="store_true",
