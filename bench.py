@@ -617,6 +617,23 @@ def run_serving_bounded(ising, rates=(25.0, 50.0, 75.0), duration=10.0, quantum=
                         f"quantum {quantum}", "highest_bounded_rate_req_s": best, "runs": runs, "unit": UNIT}
 
 
+def lane_op_fractions(res):
+    """Add, beside every rate (attempts/ns) of a secondary result, its
+    fraction of the lane-op roof (OPS_PER_ATTEMPT slots per attempt against
+    ALU_PEAK_TOPS), recursing into nested results: the plain and batched forms
+    of each workload then both carry a stated fraction of the roofline."""
+    if isinstance(res, dict):
+        out = {}
+        for k, v in res.items():
+            out[k] = lane_op_fractions(v)
+            if k in ("value", "batched_value", "plain_value") and isinstance(v, (int, float)):
+                out[k.replace("value", "lane_op_frac")] = round(OPS_PER_ATTEMPT * v / 1e3 / ALU_PEAK_TOPS, 5)
+        return out
+    if isinstance(res, list):
+        return [lane_op_fractions(x) for x in res]
+    return res
+
+
 def run_secondary(ising, name, args):
     if name == "plain4096":
         return run_plain4096(ising, plain=not args.no_plain)
@@ -738,7 +755,7 @@ def main():
         out = {}
         for name in args.only.split(","):
             log(f"only: {name}")
-            out[name] = run_secondary(ising, name, args)
+            out[name] = lane_op_fractions(run_secondary(ising, name, args))
             log(f"  {out[name]}")
         print(json.dumps({"only": out}), flush=True)
         return
@@ -752,7 +769,7 @@ def main():
     wanted = [] if args.secondary == "none" else args.secondary.split(",")
     for name in wanted:
         log(f"secondary: {name}")
-        secondary[name] = run_secondary(ising, name, args)
+        secondary[name] = lane_op_fractions(run_secondary(ising, name, args))
         log(f"  {secondary.get(name)}")
 
     cpu = None

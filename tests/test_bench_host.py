@@ -1,7 +1,8 @@
 """Host-side logic of bench.py, checked without a GPU: the refusal of more
 than one GPU, the roofline arithmetic, the word count of the headline
 lattice, the rule that drops stale HBM-traffic counters, and the batched mix
-the plain-form sample stands for."""
+the plain-form sample stands for, and the lane-op fraction every secondary
+rate carries."""
 import collections
 import json
 import os
@@ -66,3 +67,18 @@ def test_batched_mix_holds_every_size_equally():
     assert min(Ts) == pytest.approx(1.5) and max(Ts) == pytest.approx(3.5)
     assert len(set(Ts)) == 32
     assert seeds == list(range(2048))
+
+
+def test_every_secondary_rate_carries_its_lane_op_fraction():
+    # 18 lane-op slots per attempt against 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
+    res = bench.lane_op_fractions({"value": 2251.29, "unit": "attempts/ns",
+                                   "plain_same_mix": {"value": 184.46},
+                                   "runs": [{"value": 910.0, "p99_s": 0.67}],
+                                   "batched_value": 63.0, "plain_value": 0.457, "wall_s": 3.0})
+    frac = lambda v: 18 * v / (256 * 4 * 32 * 2.4)
+    assert res["lane_op_frac"] == pytest.approx(frac(2251.29), abs=1e-5)
+    assert res["plain_same_mix"]["lane_op_frac"] == pytest.approx(frac(184.46), abs=1e-5)
+    assert res["runs"][0]["lane_op_frac"] == pytest.approx(frac(910.0), abs=1e-5)
+    assert res["batched_lane_op_frac"] == pytest.approx(frac(63.0), abs=1e-5)
+    assert res["plain_lane_op_frac"] == pytest.approx(frac(0.457), abs=1e-5)
+    assert "wall_s" in res and "lane_op_frac_s" not in res  # only rates get a fraction
