@@ -1,5 +1,5 @@
 // Small lattices whose acceptance codes are drawn by the whole chip and
-// applied by one wavefront per lattice.
+// applied by one small workgroup per lattice.
 //
 // The acceptance codes of a site (Table 1's classes with the Metropolis rule
 // of Section 2 applied to its uniform) do not depend on the spins, only on
