@@ -62,17 +62,16 @@ __device__ __forceinline__ uint64_t down_of(const Nbhd& n, int I, int N, int ist
 }
 
 // New value of the word (I, J) from its neighbourhood: the 21 acceptance
-// codes from Philox blocks g = 0..4 of counter (t, I L + J) and the
+// codes from Philox blocks g = 0..4 of counter (t, c1), c1 = I L + J, and the
 // position-20 uniform u20 (drawn from the shared block 5 of the word's
 // 8-column group), then the bit-sliced flip of Table 1 and the Metropolis
 // rule.  With meas (wave-uniform), adds the word's antiparallel bonds and its
 // and its left neighbour's up spins when count (per lane) is set.
-__device__ __forceinline__ uint64_t lds_word_update(const LdsSweep& s, const RoundKeys& rk, const Nbhd& nb, int I,
-                                                    int J, uint32_t u20, bool meas, bool count, uint32_t& anti,
-                                                    uint32_t& ups) {
+__device__ __forceinline__ uint64_t lds_word_update_c1(const LdsSweep& s, const RoundKeys& rk, const Nbhd& nb, int I,
+                                                       uint32_t c1, uint32_t u20, bool meas, bool count,
+                                                       uint32_t& anti, uint32_t& ups) {
     const int n_live = s.pstar + (I <= s.istar ? 1 : 0);
     const uint64_t live = kSpinBits & (~0ull << (3 * (21 - n_live)));
-    const uint32_t c1 = (uint32_t)I * (uint32_t)s.L + (uint32_t)J;
     Codes codes = {0u, 0u, 0u};
     if (s.all_blocks) {
 #pragma unroll
@@ -109,6 +108,13 @@ __device__ __forceinline__ uint64_t lds_word_update(const LdsSweep& s, const Rou
         ups += count ? u : 0u;
     }
     return nw;
+}
+
+// The same, forming c1 from (I, J).
+__device__ __forceinline__ uint64_t lds_word_update(const LdsSweep& s, const RoundKeys& rk, const Nbhd& nb, int I,
+                                                    int J, uint32_t u20, bool meas, bool count, uint32_t& anti,
+                                                    uint32_t& ups) {
+    return lds_word_update_c1(s, rk, nb, I, (uint32_t)I * (uint32_t)s.L + (uint32_t)J, u20, meas, count, anti, ups);
 }
 
 __device__ __forceinline__ uint32_t pick4(const uint4& v, uint32_t q) {

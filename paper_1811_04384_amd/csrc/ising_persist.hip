@@ -53,6 +53,24 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 __device__ __forceinline__ uint64_t clock_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
+// LDS seen as what it is (address space 3), so that 32-bit LDS addresses
+// can be kept in registers and loaded from with no base added
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+__device__ __forceinline__ uint32_t lds_addr(const lds_u64* p) { return (uint32_t)(size_t)p; }
+__device__ __forceinline__ uint64_t lds_load64(uint32_t addr) { return *(const lds_u64*)(size_t)addr; }
+__device__ __forceinline__ void lds_store64(uint32_t addr, uint64_t v) { *(lds_u64*)(size_t)addr = v; }
+__device__ __forceinline__ uint32_t lds_load32(uint32_t addr) { return *(const lds_u32*)(size_t)addr; }
+
+// One word item of a half-sweep: the LDS addresses of the word and of its
+// neighbourhood words, the byte offset of its position-20 uniform in the
+// table of the half-sweep, its Philox counter word I L + J, its row and its
+// side (-1 interior, 0 the left boundary column, 1 the right one).
+struct WordItem {
+    uint32_t w, lf, rt, up, dn, patch, u20, c1;
+    int32_t I, side;
+};
+
 }  // namespace
 
 __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
@@ -151,12 +169,61 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
     const float rcp_P = P > 0 ? 1.0f / (float)P : 0.0f;
     const float rcp_g = 1.0f / (float)n_groups;
     const int64_t tw = a.exch_tile_words;
+    const int n_w = n_b + n_i;  // word items of a half-sweep
+    const lds_u64* T3 = (const lds_u64*)T;
+    // word item f of a half-sweep of colour c: boundary items first (items
+    // f < N/2 in column 1, the others in column w, on the rows with
+    // (I + J) % 2 == c), then the interior words row by row
+    auto make_item = [&](int f, int c) {
+        int I, x, side = -1;
+        if (f < n_b) {
+            side = f >= (N >> 1) ? 1 : 0;
+            x = side ? w : 1;
+            I = 2 * (f - side * (N >> 1)) + ((col(x) + c) & 1);
+        } else {
+            int q;
+            divmod_small(f - n_b, P, rcp_P, I, q);
+            x = whole ? 2 * q + ((I + c) & 1) : 2 + 2 * q + ((2 + gx0 + I + c) & 1);
+        }
+        const int J = col(x);
+        const int xl = whole && x == 0 ? L - 1 : x - 1;
+        const int xr = whole && x == L - 1 ? 0 : x + 1;
+        const int row = I * width;
+        WordItem it;
+        it.w = lds_addr(T3 + row + x);
+        it.lf = lds_addr(T3 + row + xl);
+        it.rt = lds_addr(T3 + row + xr);
+        it.up = lds_addr(T3 + (I > 0 ? I - 1 : N - 1) * width + x);
+        it.dn = lds_addr(T3 + (I < N - 1 ? I + 1 : 0) * width + x);
+        // the patch word (row I* for I = 0, row 0 for I = I*); other rows
+        // read row 0 and ignore it
+        it.patch = lds_addr(T3 + (I == 0 ? istar : 0) * width + x);
+        it.u20 = 16u * (uint32_t)(((J >> 3) - g_lo) * N + I) + 4u * (((uint32_t)J >> 1) & 3u);
+        it.c1 = (uint32_t)I * (uint32_t)L + (uint32_t)J;
+        it.I = I;
+        it.side = side;
+        return it;
+    };
+    // a thread's items are the same in every half-sweep of a colour: with at
+    // most two per colour (the usual tile shapes) it forms all four once
+    const bool pre = n_w <= 2 * B;
+    WordItem cur0{}, cur1{}, oth0{}, oth1{};
+    if (pre) {
+        if (tid < n_w) {
+            cur0 = make_item(tid, 0);
+            oth0 = make_item(tid, 1);
+        }
+        if (tid + B < n_w) {
+            cur1 = make_item(tid + B, 0);
+            oth1 = make_item(tid + B, 1);
+        }
+    }
     for (int hs = 0; hs < n_hs; ++hs) {
         const int c = hs & 1;
         const int j = hs >> 1;
         const LdsSweep sw = sweep_of(hs);
         const bool meas = c == 1 && a.every > 0 && ((a.sample_base + j + 1) % a.every) == 0;
-        const uint4* __restrict__ u5cur = u5tab + (size_t)(hs & 1) * n_groups * N;
+        const uint32_t u5cur_addr = lds_addr((const lds_u64*)(u5tab + (size_t)(hs & 1) * n_groups * N));
         uint4* __restrict__ u5next = u5tab + (size_t)((hs + 1) & 1) * n_groups * N;
         const int n_u = hs + 1 < n_hs ? N * n_groups : 0;
         const LdsSweep sw_next = sweep_of(hs + 1);
@@ -166,30 +233,26 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
         const uint64_t* __restrict__ gr = a.exch + (size_t)tp.right * tw + (size_t)(1 - c) * 2 * N;      // its left side
         uint64_t* __restrict__ ex = a.exch + (size_t)blockIdx.x * tw + (size_t)c * 2 * N;
         uint32_t anti = 0, ups = 0;
-        // items f = tid, tid + B, ...: the words (boundary, then interior),
-        // then the next half-sweep's position-20 blocks, in two loops so that
-        // each keeps only its own wave-uniform values live
-        int f = tid;
-        for (; f < n_b + n_i; f += B) {
-            int I, x, side = -1;
-            if (f < n_b) {  // items f < N/2: column 1 (left side), the others column w (right side)
-                side = f >= (N >> 1) ? 1 : 0;
-                x = side ? w : 1;
-                I = 2 * (f - side * (N >> 1)) + ((col(x) + c) & 1);  // rows with (I + J) % 2 == c
-            } else {
-                int q;
-                divmod_small(f - n_b, P, rcp_P, I, q);
-                x = whole ? 2 * q + ((I + c) & 1) : 2 + 2 * q + ((2 + gx0 + I + c) & 1);
+        // one word item: its neighbourhood from LDS (the ghost word of a
+        // boundary item straight from the neighbour's publication after the
+        // launch's first half-sweep), the update, and the publication of a
+        // boundary word; the last of the N boundary words raises the flag
+        // (every publisher waits for its own store first, and the exchange
+        // words and flags are device-coherent atomics, so no cache writeback
+        // or invalidation is needed)
+        auto word = [&](const WordItem& it) {
+            Nbhd nb;
+            nb.w = lds_load64(it.w);
+            nb.lf = lds_load64(it.lf);
+            nb.rt = lds_load64(it.rt);
+            nb.up = lds_load64(it.up);
+            nb.dn = lds_load64(it.dn);
+            nb.patch = lds_load64(it.patch);
+            if (it.side >= 0 && hs > 0) {
+                if (it.side == 0) nb.lf = __hip_atomic_load(&gl[it.I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else nb.rt = __hip_atomic_load(&gr[it.I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            const int J = col(x);
-            const int xl = whole && x == 0 ? L - 1 : x - 1;
-            const int xr = whole && x == L - 1 ? 0 : x + 1;
-            Nbhd nb = lds_nbhd(T, width, N, istar, I, x, xl, xr);
-            if (side >= 0 && hs > 0) {  // the ghost word comes straight from the neighbour's publication
-                if (x == 1) nb.lf = __hip_atomic_load(&gl[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (x == w) nb.rt = __hip_atomic_load(&gr[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            const uint32_t u20 = pick4(u5cur[(size_t)((J >> 3) - g_lo) * N + I], ((uint32_t)J >> 1) & 3u);
+            const uint32_t u20 = lds_load32(u5cur_addr + it.u20);
             // the sweep index made opaque to the compiler here, so that the
             // wave-uniform parts of the Philox rounds are formed per item on
             // the scalar unit instead of being hoisted out of the loop for
@@ -197,20 +260,30 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
             // vector-lane spills)
             LdsSweep swi = sw;
             asm volatile("" : "+s"(swi.t_lo), "+s"(swi.t_hi));
-            const uint64_t nw = lds_word_update(swi, rk, nb, I, J, u20, meas, true, anti, ups);
-            T[I * width + x] = nw;
-            if (side >= 0) {
-                // publish; the last of the N boundary words raises the flag
-                // (every publisher waits for its own store first, and the
-                // exchange words and flags are device-coherent atomics, so
-                // no cache writeback or invalidation is needed)
-                __hip_atomic_store(&ex[side * N + I], nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t nw = lds_word_update_c1(swi, rk, nb, it.I, it.c1, u20, meas, true, anti, ups);
+            lds_store64(it.w, nw);
+            if (it.side >= 0) {
+                __hip_atomic_store(&ex[it.side * N + it.I], nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_s_waitcnt(0);
                 if (atomicAdd(&published, 1u) == (uint32_t)(hs + 1) * (uint32_t)N - 1u)
                     __hip_atomic_store(&a.flags[blockIdx.x], 2 * t0 + (uint64_t)hs + 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
+        };
+        // items f = tid, tid + B, ...: the words (boundary, then interior),
+        // then the next half-sweep's position-20 blocks, in two loops so that
+        // each keeps only its own wave-uniform values live; the words two at
+        // a time, from the items formed at the start when there are at most
+        // two
+        for (int fw = tid; fw < n_w; fw += 2 * B) {
+            if (!pre) cur0 = make_item(fw, c);
+            word(cur0);
+            if (fw + B < n_w) {
+                if (!pre) cur1 = make_item(fw + B, c);
+                word(cur1);
+            }
         }
+        int f = tid < n_w ? tid + ((n_w - 1 - tid) / B + 1) * B : tid;  // the first item past the words
         for (; f < n_b + n_i + n_u; f += B) {
             int I, k;
             divmod_small(f - n_b - n_i, n_groups, rcp_g, I, k);
@@ -257,6 +330,13 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
             a.partials[(size_t)ord * a.n_tiles + tp.part] = {sa, su};
         }
         if (stop) break;
+        if (pre) {  // the next half-sweep has the other colour
+            const WordItem t0i = cur0, t1i = cur1;
+            cur0 = oth0;
+            cur1 = oth1;
+            oth0 = t0i;
+            oth1 = t1i;
+        }
     }
     // the ghost columns in LDS are stale past the first half-sweep, but the
     // band's own words are exact
