@@ -218,6 +218,22 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
             oth1 = make_item(tid + B, 1);
         }
     }
+    // the next half-sweep's position-20 blocks (of the rows with 21 live
+    // positions) are dealt to the threads in rank order, items rank5,
+    // rank5 + E5, ...: threads with fewer word items first, and none to the
+    // wavefronts 0, 4, 8, ... when the last round of words is partial (a
+    // workgroup's wavefronts go to the four SIMDs in turn, so those share
+    // the SIMD that carries the most rounds of words)
+    const int rows21 = pstar == 20 ? istar + 1 : 0;
+    const int r0 = n_w % B;  // threads below r0 have one word item more
+    const bool skip0 = B >= 256 && (r0 & 255) != 0;
+    auto elig_before = [&](int x) {  // eligible threads below x
+        return skip0 ? x - ((x >> 8) * 64 + min(x & 255, 64)) : x;
+    };
+    const int E5 = elig_before(B);
+    const int rank5 = skip0 && ((tid >> 6) & 3) == 0 ? -1
+                      : tid >= r0                   ? elig_before(tid) - elig_before(r0)
+                                                    : E5 - elig_before(r0) + elig_before(tid);
     for (int hs = 0; hs < n_hs; ++hs) {
         const int c = hs & 1;
         const int j = hs >> 1;
@@ -225,7 +241,7 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
         const bool meas = c == 1 && a.every > 0 && ((a.sample_base + j + 1) % a.every) == 0;
         const uint32_t u5cur_addr = lds_addr((const lds_u64*)(u5tab + (size_t)(hs & 1) * n_groups * N));
         uint4* __restrict__ u5next = u5tab + (size_t)((hs + 1) & 1) * n_groups * N;
-        const int n_u = hs + 1 < n_hs ? N * n_groups : 0;
+        const int n_u = hs + 1 < n_hs ? rows21 * n_groups : 0;
         const LdsSweep sw_next = sweep_of(hs + 1);
         // where the neighbours published the ghost words this half-sweep
         // reads: their boundary words of colour 1 - c, half-sweep hs - 1
@@ -271,10 +287,10 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
             }
         };
         // items f = tid, tid + B, ...: the words (boundary, then interior),
-        // then the next half-sweep's position-20 blocks, in two loops so that
-        // each keeps only its own wave-uniform values live; the words two at
-        // a time, from the items formed at the start when there are at most
-        // two
+        // two at a time, from the items formed at the start when there are at
+        // most two; then the next half-sweep's position-20 blocks, in a loop
+        // of their own so that each keeps only its own wave-uniform values
+        // live
         for (int fw = tid; fw < n_w; fw += 2 * B) {
             if (!pre) cur0 = make_item(fw, c);
             word(cur0);
@@ -283,11 +299,12 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
                 word(cur1);
             }
         }
-        int f = tid < n_w ? tid + ((n_w - 1 - tid) / B + 1) * B : tid;  // the first item past the words
-        for (; f < n_b + n_i + n_u; f += B) {
-            int I, k;
-            divmod_small(f - n_b - n_i, n_groups, rcp_g, I, k);
-            if (pstar + (I <= istar ? 1 : 0) == 21) u5next[(size_t)k * N + I] = block5(sw_next, rk, I, g_lo + k, c ^ 1);
+        if (rank5 >= 0) {
+            for (int b = rank5; b < n_u; b += E5) {
+                int I, k;
+                divmod_small(b, n_groups, rcp_g, I, k);
+                u5next[(size_t)k * N + I] = block5(sw_next, rk, I, g_lo + k, c ^ 1);
+            }
         }
         if (meas) {
             anti = wave_sum_u32(anti);
