@@ -3,7 +3,8 @@
 // tiles with redundant halos and the resident tiles that exchange their
 // boundary columns.  Lanes of a wavefront may hold words of different rows,
 // so the row-dependent parts (live slots, the wrap between the first and
-// last word rows, the row-(L-1) patch) are selects, not branches.
+// last word rows, the row-(L-1) patch) are selects, the last two under a
+// branch taken only by wavefronts that hold one of those rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -98,8 +99,13 @@ __device__ __forceinline__ uint64_t lds_word_update_c1(const LdsSweep& s, const 
         }
     }
     append_draw(codes, 20, u20, s.t4, s.t8);  // a dead slot when n_live < 21 (masked by live)
-    const uint64_t up = up_of(nb, I, s.sh_star);
-    const uint64_t dn = down_of(nb, I, s.N, s.istar, s.sh_star);
+    // only rows 0, N - 1 and I* wrap or take the patch: the selects run
+    // only in the wavefronts that hold such a row
+    uint64_t up = nb.up, dn = nb.dn;
+    if (I == 0 || I == s.N - 1 || I == s.istar) {
+        up = up_of(nb, I, s.sh_star);
+        dn = down_of(nb, I, s.N, s.istar, s.sh_star);
+    }
     const uint64_t nw = nb.w ^ flip_mask(nb.w, up, dn, nb.lf, nb.rt, assemble_codes(codes), live);
     if (meas) {
         uint32_t a = 0, u = 0;

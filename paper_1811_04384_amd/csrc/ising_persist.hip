@@ -220,10 +220,12 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
     }
     // the next half-sweep's position-20 blocks (of the rows with 21 live
     // positions) are dealt to the threads in rank order, items rank5,
-    // rank5 + E5, ...: threads with fewer word items first, and none to the
-    // wavefronts 0, 4, 8, ... when the last round of words is partial (a
-    // workgroup's wavefronts go to the four SIMDs in turn, so those share
-    // the SIMD that carries the most rounds of words)
+    // rank5 + E5, ...  When the last round of words is partial, none go to
+    // the wavefronts 0, 4, 8, ... (a workgroup's wavefronts go to the four
+    // SIMDs in turn, so those share the SIMD that carries the most rounds
+    // of words) and threads with fewer word items come first; otherwise the
+    // threads in order (the oldest wavefronts, which the instruction arbiter
+    // favours, first).  Both orders were the faster one in their case.
     const int rows21 = pstar == 20 ? istar + 1 : 0;
     const int r0 = n_w % B;  // threads below r0 have one word item more
     const bool skip0 = B >= 256 && (r0 & 255) != 0;
@@ -231,7 +233,8 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
         return skip0 ? x - ((x >> 8) * 64 + min(x & 255, 64)) : x;
     };
     const int E5 = elig_before(B);
-    const int rank5 = skip0 && ((tid >> 6) & 3) == 0 ? -1
+    const int rank5 = !skip0                       ? tid
+                      : ((tid >> 6) & 3) == 0       ? -1
                       : tid >= r0                   ? elig_before(tid) - elig_before(r0)
                                                     : E5 - elig_before(r0) + elig_before(tid);
     for (int hs = 0; hs < n_hs; ++hs) {
