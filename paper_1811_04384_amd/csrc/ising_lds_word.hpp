@@ -62,6 +62,17 @@ __device__ __forceinline__ uint64_t down_of(const Nbhd& n, int I, int N, int ist
     return I == istar ? patched : d;
 }
 
+// The sums of measure_word with fewer counts: live has only the spin bit 3k
+// of each field, so the masked bond words for up and down shifted by one
+// and two bits fill the two free bits of every field, and one count covers
+// three of them (likewise for the two up-spin counts).
+__device__ __forceinline__ void measure_word_packed(uint64_t w, uint64_t up, uint64_t dn, uint64_t lf, uint64_t rt,
+                                                    uint64_t live, uint32_t& anti, uint32_t& ups) {
+    const uint64_t b3 = ((w ^ lf) & live) | (((w ^ up) & live) << 1) | (((w ^ dn) & live) << 2);
+    anti += __popcll(b3) + __popcll((w ^ rt) & live);
+    ups += __popcll((w & live) | ((lf & live) << 1));
+}
+
 // New value of the word (I, J) from its neighbourhood: the 21 acceptance
 // codes from Philox blocks g = 0..4 of counter (t, c1), c1 = I L + J, and the
 // position-20 uniform u20 (drawn from the shared block 5 of the word's
@@ -109,7 +120,7 @@ __device__ __forceinline__ uint64_t lds_word_update_c1(const LdsSweep& s, const 
     const uint64_t nw = nb.w ^ flip_mask(nb.w, up, dn, nb.lf, nb.rt, assemble_codes(codes), live);
     if (meas) {
         uint32_t a = 0, u = 0;
-        measure_word(nw, up, dn, nb.lf, nb.rt, live, a, u);
+        measure_word_packed(nw, up, dn, nb.lf, nb.rt, live, a, u);
         anti += count ? a : 0u;
         ups += count ? u : 0u;
     }
