@@ -237,11 +237,17 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
                       : ((tid >> 6) & 3) == 0       ? -1
                       : tid >= r0                   ? elig_before(tid) - elig_before(r0)
                                                     : E5 - elig_before(r0) + elig_before(tid);
+    // the launch's next sampled sweep (a sample after sweep j iff
+    // (sample_base + j + 1) % every == 0; -1 for none) and the samples taken
+    // so far: counted, not divided out per half-sweep (a 64-bit division is
+    // a long scalar routine)
+    int64_t next_sample = a.every > 0 ? (int64_t)a.every - 1 - a.sample_base % a.every : -1;
+    int n_taken = 0;
     for (int hs = 0; hs < n_hs; ++hs) {
         const int c = hs & 1;
         const int j = hs >> 1;
         const LdsSweep sw = sweep_of(hs);
-        const bool meas = c == 1 && a.every > 0 && ((a.sample_base + j + 1) % a.every) == 0;
+        const bool meas = c == 1 && j == next_sample;
         const uint32_t u5cur_addr = lds_addr((const lds_u64*)(u5tab + (size_t)(hs & 1) * n_groups * N));
         uint4* __restrict__ u5next = u5tab + (size_t)((hs + 1) & 1) * n_groups * N;
         const int n_u = hs + 1 < n_hs ? rows21 * n_groups : 0;
@@ -345,9 +351,11 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
                 sa += red[2 * wv];
                 su += red[2 * wv + 1];
             }
-            // samples of this launch before this one: multiples of `every` in (sample_base, sample_base + j]
-            const int64_t ord = (a.sample_base + j) / a.every - a.sample_base / a.every;
-            a.partials[(size_t)ord * a.n_tiles + tp.part] = {sa, su};
+            a.partials[(size_t)n_taken * a.n_tiles + tp.part] = {sa, su};
+        }
+        if (meas) {
+            next_sample += a.every;
+            ++n_taken;
         }
         if (stop) break;
         if (pre) {  // the next half-sweep has the other colour

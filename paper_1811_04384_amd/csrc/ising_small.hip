@@ -71,6 +71,8 @@ __global__ void __launch_bounds__(kSmallMaxBlock) k_small(const LatticeDesc* __r
     const int half = L >> 1;  // words of one colour per row
     __syncthreads();
 
+    // the next sampled local sweep, counted rather than divided out per sweep
+    int64_t next_sample = every > 0 ? every - 1 : -1;
     for (int s0 = 0; s0 < n_sweeps; s0 += batch) {
         const int nb = min(batch, n_sweeps - s0);
         // draws: item (sweep, colour, row, group) -> the codes of the group's
@@ -117,8 +119,8 @@ __global__ void __launch_bounds__(kSmallMaxBlock) k_small(const LatticeDesc* __r
         __syncthreads();
         // the sweeps of the batch, from LDS
         for (int j = 0; j < nb; ++j) {
-            const int s = s0 + j;
-            const bool meas = every > 0 && ((s + 1) % every) == 0;
+            const bool meas = s0 + j == next_sample;
+            if (meas) next_sample += every;
             const uint64_t* __restrict__ cj = codes + (size_t)j * NL;
             for (int c = 0; c < 2; ++c) {
                 uint32_t anti = 0, ups = 0;
