@@ -287,7 +287,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
         if (g.L <= p.tile_max_L && p.tile_exchange) {
             // resident tiles, as long as all of them fit on the device at once
             const int32_t w = p.tile_cols >= g.L ? g.L : p.tile_cols;
-            const size_t lds = persist_lds_bytes(g.L, g.N, w);
+            const size_t lds = persist_lds_bytes(g.L, g.N, w, p.tile_block);
             int64_t capacity = 0;
             if (lds <= res_limit) ISING_HIP(persist_capacity(p.tile_block, std::max(lds, b->res_lds), b->device, &capacity));
             const int32_t nt = (g.L + w - 1) / w;

@@ -732,7 +732,7 @@ int ising_set_resident_tiles(ising_lattice* h, int32_t tile_cols, int32_t block,
     if (max_sweeps < 1 || max_sweeps > kResidentMaxSweeps)
         return fail(ISING_EINVAL, "ising_set_resident_tiles: max_sweeps must be in [1, %d]", kResidentMaxSweeps);
     const int32_t w = tile_cols >= L ? L : tile_cols;
-    const size_t lds = persist_lds_bytes(L, N, w);
+    const size_t lds = persist_lds_bytes(L, N, w, block);
     if (lds > persist_lds_limit(h->device))
         return fail(ISING_EINVAL, "ising_set_resident_tiles: a tile needs %zu bytes of LDS, %zu available", lds,
                     persist_lds_limit(h->device));

@@ -143,9 +143,10 @@ hipError_t launch_finalize_tiles(const LatticeDesc* descs, LatticeState* states,
 
 // ---- resident LDS tiles with boundary exchange -------------------------------
 
-// Dynamic LDS of one resident tile of interior width w (w >= L: the whole
-// lattice); the limit and the one-time attribute as for the tiles above.
-size_t persist_lds_bytes(int32_t L, int32_t N, int32_t w);
+// Dynamic LDS of the resident tiles of a lattice cut into bands of w word
+// columns (w >= L: the whole lattice) for workgroups of `block` threads;
+// the limit and the one-time attribute as for the tiles above.
+size_t persist_lds_bytes(int32_t L, int32_t N, int32_t w, int32_t block);
 size_t persist_lds_limit(int device);
 hipError_t allow_persist_lds(int device);
 // How many resident tiles of `block` threads and lds_bytes of LDS the device

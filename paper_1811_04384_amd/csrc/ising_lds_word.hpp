@@ -73,18 +73,12 @@ __device__ __forceinline__ void measure_word_packed(uint64_t w, uint64_t up, uin
     ups += __popcll((w & live) | ((lf & live) << 1));
 }
 
-// New value of the word (I, J) from its neighbourhood: the 21 acceptance
-// codes from Philox blocks g = 0..4 of counter (t, c1), c1 = I L + J, and the
-// position-20 uniform u20 (drawn from the shared block 5 of the word's
-// 8-column group), then the bit-sliced flip of Table 1 and the Metropolis
-// rule.  With meas (wave-uniform), adds the word's antiparallel bonds and its
-// and its left neighbour's up spins when count (per lane) is set.
-__device__ __forceinline__ uint64_t lds_word_update_c1(const LdsSweep& s, const RoundKeys& rk, const Nbhd& nb, int I,
-                                                       uint32_t c1, uint32_t u20, bool meas, bool count,
-                                                       uint32_t& anti, uint32_t& ups) {
-    const int n_live = s.pstar + (I <= s.istar ? 1 : 0);
-    const uint64_t live = kSpinBits & (~0ull << (3 * (21 - n_live)));
-    Codes codes = {0u, 0u, 0u};
+// The acceptance codes of positions 0..19 of the word with Philox counter
+// word c1 = I L + J at sweep t: blocks g = 0..4 of counter (t, c1), four
+// positions each (blocks past the last live position skipped on small
+// lattices, whose rows have at most 16 live positions).
+__device__ __forceinline__ void lds_word_codes19(const LdsSweep& s, const RoundKeys& rk, int n_live, uint32_t c1,
+                                                 Codes& codes) {
     if (s.all_blocks) {
 #pragma unroll
         for (int g = 0; g < 5; ++g) {
@@ -94,7 +88,7 @@ __device__ __forceinline__ uint64_t lds_word_update_c1(const LdsSweep& s, const 
             append_draw(codes, 4 * g + 2, r.z, s.t4, s.t8);
             append_draw(codes, 4 * g + 3, r.w, s.t4, s.t8);
         }
-    } else {  // small lattices: blocks past the last live position are skipped
+    } else {
 #pragma unroll
         for (int g = 0; g < 5; ++g) {
             if (4 * g < n_live) {
@@ -109,7 +103,15 @@ __device__ __forceinline__ uint64_t lds_word_update_c1(const LdsSweep& s, const 
             }
         }
     }
-    append_draw(codes, 20, u20, s.t4, s.t8);  // a dead slot when n_live < 21 (masked by live)
+}
+
+// The bit-sliced flip of Table 1 and the Metropolis rule applied to the word
+// with the assembled codes of all its positions; with meas (wave-uniform),
+// adds the word's antiparallel bonds and its and its left neighbour's up
+// spins when count (per lane) is set.
+__device__ __forceinline__ uint64_t lds_word_flip(const LdsSweep& s, const Nbhd& nb, int I, uint64_t live,
+                                                  uint64_t codes, bool meas, bool count, uint32_t& anti,
+                                                  uint32_t& ups) {
     // only rows 0, N - 1 and I* wrap or take the patch: the selects run
     // only in the wavefronts that hold such a row
     uint64_t up = nb.up, dn = nb.dn;
@@ -117,7 +119,7 @@ __device__ __forceinline__ uint64_t lds_word_update_c1(const LdsSweep& s, const 
         up = up_of(nb, I, s.sh_star);
         dn = down_of(nb, I, s.N, s.istar, s.sh_star);
     }
-    const uint64_t nw = nb.w ^ flip_mask(nb.w, up, dn, nb.lf, nb.rt, assemble_codes(codes), live);
+    const uint64_t nw = nb.w ^ flip_mask(nb.w, up, dn, nb.lf, nb.rt, codes, live);
     if (meas) {
         uint32_t a = 0, u = 0;
         measure_word_packed(nw, up, dn, nb.lf, nb.rt, live, a, u);
@@ -125,6 +127,42 @@ __device__ __forceinline__ uint64_t lds_word_update_c1(const LdsSweep& s, const 
         ups += count ? u : 0u;
     }
     return nw;
+}
+
+__device__ __forceinline__ uint64_t live_mask(const LdsSweep& s, int I) {
+    const int n_live = s.pstar + (I <= s.istar ? 1 : 0);
+    return kSpinBits & (~0ull << (3 * (21 - n_live)));
+}
+
+// New value of the word (I, J) from its neighbourhood: the 21 acceptance
+// codes, those of positions 0..19 as above and that of position 20 from the
+// uniform u20 (drawn from the shared block 5 of the word's 8-column group),
+// then the flip.
+__device__ __forceinline__ uint64_t lds_word_update_c1(const LdsSweep& s, const RoundKeys& rk, const Nbhd& nb, int I,
+                                                       uint32_t c1, uint32_t u20, bool meas, bool count,
+                                                       uint32_t& anti, uint32_t& ups) {
+    Codes codes = {0u, 0u, 0u};
+    lds_word_codes19(s, rk, s.pstar + (I <= s.istar ? 1 : 0), c1, codes);
+    append_draw(codes, 20, u20, s.t4, s.t8);  // a dead slot when n_live < 21 (masked by live)
+    return lds_word_flip(s, nb, I, live_mask(s, I), assemble_codes(codes), meas, count, anti, ups);
+}
+
+// The codes of positions 0..19 of a word, assembled, with field 0 (position
+// 20) left 0: drawn ahead of the word's update.
+__device__ __forceinline__ uint64_t lds_word_codes(const LdsSweep& s, const RoundKeys& rk, int I, uint32_t c1) {
+    Codes codes = {0u, 0u, 0u};
+    lds_word_codes19(s, rk, s.pstar + (I <= s.istar ? 1 : 0), c1, codes);
+    append_code(codes, 20, 0u);
+    return assemble_codes(codes);
+}
+
+// The update of a word whose codes of positions 0..19 were drawn ahead:
+// the code of position 20 from u20 joins them in field 0.
+__device__ __forceinline__ uint64_t lds_word_apply(const LdsSweep& s, const Nbhd& nb, int I, uint64_t codes19,
+                                                   uint32_t u20, bool meas, bool count, uint32_t& anti,
+                                                   uint32_t& ups) {
+    const uint64_t codes = codes19 | first_accept(u20, s.t4, s.t8);  // a dead slot when n_live < 21
+    return lds_word_flip(s, nb, I, live_mask(s, I), codes, meas, count, anti, ups);
 }
 
 // The same, forming c1 from (I, J).

@@ -37,6 +37,8 @@
 // wraps them there: no exchange at all.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ising_device.hpp"
 #include "ising_launch.hpp"
 #include "ising_lds_word.hpp"
@@ -69,7 +71,9 @@ __device__ __forceinline__ uint32_t lds_load32(uint32_t addr) { return *(const l
 struct WordItem {
     uint32_t w, lf, rt, up, dn, patch, u20, c1;
     int32_t I, side;
+    uint32_t code;  // byte offset of its codes in a half-sweep's code table
 };
+
 
 }  // namespace
 
@@ -202,12 +206,27 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
         it.c1 = (uint32_t)I * (uint32_t)L + (uint32_t)J;
         it.I = I;
         it.side = side;
+        it.code = 8u * (uint32_t)f;
         return it;
     };
-    // a thread's items are the same in every half-sweep of a colour: with at
-    // most two per colour (the usual tile shapes) it forms all four once
+    // With at most two word items per thread and colour (the usual tile
+    // shapes), every thread's items are the same in every half-sweep of a
+    // colour and are formed once, and the codes of positions 0..19 of every
+    // word are drawn a half-sweep ahead into a code table (two, by the
+    // half-sweep's parity, after the position-20 tables): in a half-sweep a
+    // thread updates its words from the table and draws the codes of its
+    // words of the other colour for the next one, while the loads of the
+    // word's neighbourhood are in flight.  Otherwise every item is formed
+    // and drawn in its half-sweep.
     const bool pre = n_w <= 2 * B;
-    WordItem cur0{}, cur1{}, oth0{}, oth1{};
+    const uint32_t ctab = lds_addr((const lds_u64*)(u5tab + (size_t)2 * n_groups * N));
+    WordItem cur0{}, cur1{}, oth0{}, oth1{};  // word items, this colour and the other
+    auto draw_codes = [&](const WordItem& it, const LdsSweep& swc, uint32_t table) {
+        // the sweep index made opaque to the compiler (see the words below)
+        LdsSweep swi = swc;
+        asm volatile("" : "+s"(swi.t_lo), "+s"(swi.t_hi));
+        lds_store64(table + it.code, lds_word_codes(swi, rk, it.I, it.c1));
+    };
     if (pre) {
         if (tid < n_w) {
             cur0 = make_item(tid, 0);
@@ -217,6 +236,11 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
             cur1 = make_item(tid + B, 0);
             oth1 = make_item(tid + B, 1);
         }
+        // the codes of the first half-sweep
+        const LdsSweep sw0 = sweep_of(0);
+        if (tid < n_w) draw_codes(cur0, sw0, ctab);
+        if (tid + B < n_w) draw_codes(cur1, sw0, ctab);
+        __syncthreads();
     }
     // the next half-sweep's position-20 blocks (of the rows with 21 live
     // positions) are dealt to the threads in rank order, items rank5,
@@ -260,12 +284,16 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
         uint32_t anti = 0, ups = 0;
         // one word item: its neighbourhood from LDS (the ghost word of a
         // boundary item straight from the neighbour's publication after the
-        // launch's first half-sweep), the update, and the publication of a
-        // boundary word; the last of the N boundary words raises the flag
-        // (every publisher waits for its own store first, and the exchange
-        // words and flags are device-coherent atomics, so no cache writeback
-        // or invalidation is needed)
-        auto word = [&](const WordItem& it) {
+        // launch's first half-sweep) and the word `early` gives, then
+        // `between` (while the loads are in flight), the update (by `update`,
+        // from the neighbourhood, the position-20 uniform and that word),
+        // and the publication of a boundary word; the
+        // last of the N boundary words raises the flag (every publisher waits
+        // for its own store first, and the exchange words and flags are
+        // device-coherent atomics, so no cache writeback or invalidation is
+        // needed).  The loads of an item that does not exist (valid false)
+        // read LDS at the item's default address 0 and are not used.
+        auto word = [&](const WordItem& it, bool valid, auto early, auto between, auto update) {
             Nbhd nb;
             nb.w = lds_load64(it.w);
             nb.lf = lds_load64(it.lf);
@@ -273,19 +301,15 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
             nb.up = lds_load64(it.up);
             nb.dn = lds_load64(it.dn);
             nb.patch = lds_load64(it.patch);
+            const uint32_t u20 = lds_load32(u5cur_addr + it.u20);
+            const uint64_t e = early(it);
+            if (!valid) return;
             if (it.side >= 0 && hs > 0) {
                 if (it.side == 0) nb.lf = __hip_atomic_load(&gl[it.I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 else nb.rt = __hip_atomic_load(&gr[it.I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            const uint32_t u20 = lds_load32(u5cur_addr + it.u20);
-            // the sweep index made opaque to the compiler here, so that the
-            // wave-uniform parts of the Philox rounds are formed per item on
-            // the scalar unit instead of being hoisted out of the loop for
-            // all five blocks (which overflows the scalar registers into
-            // vector-lane spills)
-            LdsSweep swi = sw;
-            asm volatile("" : "+s"(swi.t_lo), "+s"(swi.t_hi));
-            const uint64_t nw = lds_word_update_c1(swi, rk, nb, it.I, it.c1, u20, meas, true, anti, ups);
+            between();
+            const uint64_t nw = update(it, nb, u20, e);
             lds_store64(it.w, nw);
             if (it.side >= 0) {
                 __hip_atomic_store(&ex[it.side * N + it.I], nw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -295,19 +319,36 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
         };
-        // items f = tid, tid + B, ...: the words (boundary, then interior),
-        // two at a time, from the items formed at the start when there are at
-        // most two; then the next half-sweep's position-20 blocks, in a loop
-        // of their own so that each keeps only its own wave-uniform values
-        // live
-        for (int fw = tid; fw < n_w; fw += 2 * B) {
-            if (!pre) cur0 = make_item(fw, c);
-            word(cur0);
-            if (fw + B < n_w) {
-                if (!pre) cur1 = make_item(fw + B, c);
-                word(cur1);
-            }
+        if (pre) {
+            // the words from the code table of this half-sweep; meanwhile the
+            // codes of the same threads' words of the other colour for the
+            // next half-sweep into the other table
+            const uint32_t ccur = ctab + (uint32_t)(hs & 1) * 8u * (uint32_t)n_w;
+            const uint32_t cnext = ctab + (uint32_t)((hs + 1) & 1) * 8u * (uint32_t)n_w;
+            const bool draw = hs + 1 < n_hs;
+            auto codes = [&](const WordItem& it) { return lds_load64(ccur + it.code); };
+            auto from_table = [&](const WordItem& it, const Nbhd& nb, uint32_t u20, uint64_t cd) {
+                return lds_word_apply(sw, nb, it.I, cd, u20, meas, true, anti, ups);
+            };
+            word(cur0, tid < n_w, codes, [&] { if (draw) draw_codes(oth0, sw_next, cnext); }, from_table);
+            word(cur1, tid + B < n_w, codes, [&] { if (draw) draw_codes(oth1, sw_next, cnext); }, from_table);
+        } else {
+            // the words f = tid, tid + B, ..., each drawing its own codes:
+            // the sweep index made opaque to the compiler, so that the
+            // wave-uniform parts of the Philox rounds are formed per item on
+            // the scalar unit instead of being hoisted out of the loop for
+            // all five blocks (which overflows the scalar registers into
+            // vector-lane spills)
+            auto drawing = [&](const WordItem& it, const Nbhd& nb, uint32_t u20, uint64_t) {
+                LdsSweep swi = sw;
+                asm volatile("" : "+s"(swi.t_lo), "+s"(swi.t_hi));
+                return lds_word_update_c1(swi, rk, nb, it.I, it.c1, u20, meas, true, anti, ups);
+            };
+            auto none = [](const WordItem&) { return 0ull; };
+            for (int fw = tid; fw < n_w; fw += B) word(make_item(fw, c), true, none, [] {}, drawing);
         }
+        // then the next half-sweep's position-20 blocks, in a loop of their
+        // own so that it keeps only its own wave-uniform values live
         if (rank5 >= 0) {
             for (int b = rank5; b < n_u; b += E5) {
                 int I, k;
@@ -382,11 +423,22 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
     }
 }
 
-size_t persist_lds_bytes(int32_t L, int32_t N, int32_t w) {
-    const bool whole = w >= L;
-    const int64_t width = whole ? L : (int64_t)w + 2;
-    const int64_t groups = whole ? (L + 7) / 8 : w / 8 + 2;
-    return (size_t)(8 * (int64_t)N * width + 2 * 16 * groups * (int64_t)N);
+size_t persist_lds_bytes(int32_t L, int32_t N, int32_t w, int32_t block) {
+    // a tile of width wi: its band with the ghost columns, two position-20
+    // tables (a bound on their groups) and, with at most two word items per
+    // thread and colour, two code tables; the widest need of the lattice's
+    // tiles (all of width w but the last)
+    auto need = [&](int64_t wi) {
+        const bool whole = wi >= L;
+        const int64_t width = whole ? L : wi + 2;
+        const int64_t groups = whole ? (L + 7) / 8 : wi / 8 + 2;
+        const int64_t items = (int64_t)N * (whole ? L : wi) / 2;
+        const int64_t codes = items <= 2 * (int64_t)block ? 16 * items : 0;
+        return (size_t)(8 * (int64_t)N * width + 2 * 16 * groups * (int64_t)N + codes);
+    };
+    const int64_t wf = w >= L ? L : w;
+    const int64_t last = L - ((L + wf - 1) / wf - 1) * wf;
+    return std::max(need(wf), need(last));
 }
 
 size_t persist_lds_limit(int device) {
