@@ -8,7 +8,8 @@ oracle's.  Cases: the whole lattice in one workgroup (no exchange), many
 bands, two bands (each the other's left and right neighbour), ragged last
 bands down to two columns, L not a multiple of 8 or of 21, the paper's
 L = 21 N lattices, samples spanning launches (calls longer than one launch),
-and workgroups of 64 to 1024 threads.
+workgroups of 64 to 1024 threads, and both ways of drawing the codes (per
+word item in its half-sweep, or a half-sweep ahead into LDS code tables).
 """
 import pytest
 
@@ -42,6 +43,15 @@ CASES = [
     (1006, 4, True, 48, 512, 5),
     (1008, 21, True, 48, 512, 9),
     (2016, 22, True, 96, 1024, 4),
+    # at most two words of a colour per thread: items formed once per launch
+    # and codes drawn a half-sweep ahead (two rounds on two wavefronts; the
+    # heating scan's bands, 24 even rounds)
+    (168, 3, False, 40, 128, 6),
+    (1008, 25, True, 64, 1024, 5),
+    # wide bands with more words per thread and a narrow last band with at
+    # most two (its code tables must fit the LDS reserved for the wide ones)
+    (1008, 23, True, 22, 256, 3),
+    (1010, 24, False, 32, 256, 4),
 ]
 
 
