@@ -17,7 +17,10 @@
 //     that publishes the last of them raises the tile's flag (to a value
 //     that grows with the lattice's sweep counter and the half-sweep);
 //   - then the interior words (columns 2 .. w - 1), while the boundary words
-//     travel, and the Philox blocks of the next half-sweep's position 20;
+//     travel, and the Philox blocks of the next half-sweep's position 20
+//     (and, with at most two words of a colour per thread, the acceptance
+//     codes of the next half-sweep's words, drawn into an LDS code table
+//     while each word's own loads are in flight);
 //   - at the end, before the workgroup barrier, one thread waits until both
 //     neighbours' flags show this half-sweep (their publications are
 //     normally done long before).
