@@ -17,7 +17,9 @@ scans of L = 1008 replicas with the lattice carried over (energy and specific
 heat per temperature), the paper's own 101-temperature scan of its L = 84
 lattice, the paper's three Table 2 cases run with its own random-pick strip
 dynamics, 21 replicas of L = 8192 packed field by field into one word
-lattice, and a served request stream with p50/p99 latency.
+lattice, and a served request stream with p50/p99 latency (as specified,
+at lower rates, and with a device-memory budget small enough that admission
+by footprint binds).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -538,10 +540,11 @@ def run_replicas(ising, L=8192, sweeps=200, seed=21):
 
 
 SERVING_RATE, SERVING_DURATION, SERVING_QUANTUM, SERVING_SLOTS = 200.0, 60.0, 200, 128
+SERVING_BUDGET = 16 << 30
 
 
 def run_serving(ising, rate=SERVING_RATE, duration=SERVING_DURATION, quantum=SERVING_QUANTUM, seed=2026,
-                slots=SERVING_SLOTS):
+                slots=SERVING_SLOTS, hbm_budget=SERVING_BUDGET):
     """Poisson request stream: L = 2^U{7..12}, T ~ U[1.5, 3.5], sweeps ~
     U{1000..20000}, hot start with seed = request id; continuous batching.
     Latency runs from a request's submission to the read-back of its result;
@@ -561,7 +564,8 @@ def run_serving(ising, rate=SERVING_RATE, duration=SERVING_DURATION, quantum=SER
         arrivals.append((t, rid, int(2 ** rng.integers(7, 13)), float(rng.uniform(1.5, 3.5)),
                          int(rng.integers(1000, 20001))))
         rid += 1
-    srv = ising.Server(hbm_budget=16 << 30, max_slots=slots, quantum_sweeps=quantum)
+    srv = ising.Server(hbm_budget=hbm_budget, max_slots=slots, quantum_sweeps=quantum)
+    peak_bytes = peak_resident = 0
     lat_s = []
     attempts = 0
     i = 0
@@ -580,6 +584,9 @@ def run_serving(ising, rate=SERVING_RATE, duration=SERVING_DURATION, quantum=SER
             srv.submit(r, L, T, sw)
             i += 1
         active = srv.step()
+        st = srv.stats()
+        peak_bytes = max(peak_bytes, st["bytes_in_use"])
+        peak_resident = max(peak_resident, st["resident"])
         for r in srv.poll():
             lat_s.append(r["t_done_s"] - r["t_submit_s"])
             attempts += r["L"] * r["L"] * r["sweeps"]
@@ -592,7 +599,8 @@ def run_serving(ising, rate=SERVING_RATE, duration=SERVING_DURATION, quantum=SER
     offered = sum(a[2] * a[2] * a[4] for a in arrivals) / (duration * 1e9)
     return {"workload": f"Poisson {rate:g} req/s for {duration:g} s, L=2^U{{7..12}}, T~U[1.5,3.5], "
                         f"sweeps~U{{1000..20000}}, hot start seed = request id",
-            "quantum_sweeps": quantum, "resident_slots": slots,
+            "quantum_sweeps": quantum, "resident_slots": slots, "hbm_budget_bytes": hbm_budget,
+            "peak_bytes_in_use": peak_bytes, "peak_resident": peak_resident,
             "requests": len(arrivals), "p50_s": round(float(np.percentile(lat, 50)), 3),
             "p99_s": round(float(np.percentile(lat, 99)), 3), "throughput_req_s": round(len(arrivals) / wall, 2),
             "value": round(attempts / (wall * 1e9), 2), "unit": UNIT, "wall_s": round(wall, 2),
@@ -615,6 +623,22 @@ def run_serving_bounded(ising, rates=(25.0, 50.0, 75.0), duration=10.0, quantum=
             best = rate
     return {"workload": f"the served stream at {', '.join(f'{x:g}' for x in rates)} req/s for {duration:g} s each, "
                         f"quantum {quantum}", "highest_bounded_rate_req_s": best, "runs": runs, "unit": UNIT}
+
+
+def run_serving_small_budget(ising, rate=50.0, duration=10.0, quantum=100, budget=64 << 20):
+    """The 50 req/s stream once with the default device-memory budget and
+    once with a budget of 64 MiB, which holds about 45 requests of the mean
+    footprint (1.4 MB) and 9 of the largest (L = 4096, 6.4 MB): admission by
+    footprint then binds before the 128 slots do, and the requests wait in
+    the queue for memory instead."""
+    out = {"workload": f"Poisson {rate:g} req/s for {duration:g} s (the served stream), device-memory budget "
+                       f"{SERVING_BUDGET >> 30} GiB against {budget >> 20} MiB, quantum {quantum}", "unit": UNIT}
+    for name, b in (("default_budget", SERVING_BUDGET), ("small_budget", budget)):
+        log(f"  serving at {rate:g} req/s with a budget of {b >> 20} MiB")
+        r = run_serving(ising, rate, duration, quantum, hbm_budget=b)
+        out[name] = {k: r[k] for k in ("hbm_budget_bytes", "peak_bytes_in_use", "peak_resident", "p50_s", "p99_s",
+                                       "drain_s", "throughput_req_s", "value")}
+    return out
 
 
 def lane_op_fractions(res):
@@ -653,6 +677,8 @@ def run_secondary(ising, name, args):
         return run_replicas(ising)
     if name == "serving_bounded":
         return run_serving_bounded(ising)
+    if name == "serving_small_budget":
+        return run_serving_small_budget(ising)
     if name == "serving":
         return run_serving(ising, args.serving_rate, args.serving_duration, args.serving_quantum,
                            slots=args.serving_slots)
@@ -668,7 +694,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--secondary",
                     default="plain4096,graph4096,batched,scan64,heating_scan,paper_scan,paper_cases,replicas,"
-                            "serving_bounded,serving",
+                            "serving_bounded,serving_small_budget,serving",
                     help="comma list of secondary workloads, or 'none'")
     ap.add_argument("--serving-rate", type=float, default=SERVING_RATE)
     ap.add_argument("--serving-duration", type=float, default=SERVING_DURATION)
