@@ -259,9 +259,13 @@ __global__ void __launch_bounds__(64) k_strip_apply(uint64_t* __restrict__ W, St
             bool conflict = false;
             uint64_t vw = 0, vlf = 0, vrt = 0, vup = 0, vdn = 0, vpatch = 0, vlive = 0;
             if (act) {
+                // all twelve loads in flight together: the claims combined
+                // without short-circuit, which would make six dependent round
+                // trips of them
                 const uint32_t ui = (uint32_t)i;
-                conflict = my_claim[w] < ui || my_claim[lf] < ui || my_claim[rt] < ui || my_claim[up] < ui ||
-                           my_claim[dn] < ui || my_claim[patch] < ui;
+                const uint32_t c_w = my_claim[w], c_lf = my_claim[lf], c_rt = my_claim[rt], c_up = my_claim[up],
+                               c_dn = my_claim[dn], c_pa = my_claim[patch];
+                conflict = (c_w < ui) | (c_lf < ui) | (c_rt < ui) | (c_up < ui) | (c_dn < ui) | (c_pa < ui);
                 vw = my[w];
                 vlf = my[lf];
                 vrt = my[rt];
