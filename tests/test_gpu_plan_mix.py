@@ -1,4 +1,4 @@
-"""Seeded random mixes of lattices and execution plans, each lattice's series,
+"""Seeded random mixes of lattices and execution plans (32 cases), each lattice's series,
 state and sums against the oracle: every plan kind of the batch engine (half-
 sweep launches, one workgroup per lattice, halo tiles, resident tiles, codes
 drawn chip-wide) combined at random with lattice sizes (L not a multiple of
@@ -32,8 +32,8 @@ def _random_plan(rng, Ls):
              sweeps_per_graph=rng.randint(1, 9), draw_sweeps=rng.choice([0, 0, 1, 3, 8]))
     kind = rng.choice(["none", "halo", "resident"])
     if kind != "none":
-        p.update(tile_max_L=rng.choice([Lmax, 128]), tile_cols=rng.choice([2, 8, 16, 32]),
-                 tile_block=rng.choice([64, 256, 512]))
+        p.update(tile_max_L=rng.choice([Lmax, 128]), tile_cols=rng.choice([2, 8, 16, 22, 32, 64]),
+                 tile_block=rng.choice([64, 128, 256, 512, 1024]))
         if kind == "halo":
             p.update(tile_sweeps=rng.randint(1, 4), tile_exchange=0)
         else:
@@ -41,7 +41,7 @@ def _random_plan(rng, Ls):
     return p
 
 
-@pytest.mark.parametrize("case", range(16))
+@pytest.mark.parametrize("case", range(32))
 def test_random_plan_mix_matches_oracle(case):
     rng = random.Random(1000 + case)
     n = rng.randint(2, 6)
