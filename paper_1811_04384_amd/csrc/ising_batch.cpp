@@ -71,6 +71,8 @@ struct ising_batch {
     TileWork* d_tiles = nullptr;
     int32_t n_tiles = 0;
     Partial* d_tile_part = nullptr;  // kTileMaxSweeps x n_tiles
+    uint64_t* d_halo = nullptr;      // n_tiles x halo_stride: halo copies of the tiles narrower than their lattice
+    int64_t halo_stride = 0;
     int32_t* d_ids_tile = nullptr;
     int32_t n_tile_lat = 0;
     std::vector<std::pair<Geometry, int32_t>> tile_shapes;  // distinct (geometry, tile width) of the tiles
@@ -124,6 +126,7 @@ void release(ising_batch* b) {
     free_dev(b->d_stage);
     free_dev(b->d_tiles);
     free_dev(b->d_tile_part);
+    free_dev(b->d_halo);
     free_dev(b->d_ids_tile);
     free_dev(b->d_res);
     free_dev(b->d_exch);
@@ -237,6 +240,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     free_dev(b->d_ids_glb);
     free_dev(b->d_tiles);
     free_dev(b->d_tile_part);
+    free_dev(b->d_halo);
     free_dev(b->d_ids_tile);
     free_dev(b->d_res);
     free_dev(b->d_exch);
@@ -259,6 +263,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     const size_t tile_limit = tile_lds_limit(b->device);
     std::vector<int32_t> ids_tile;
     std::vector<TileWork> tiles;
+    int64_t halo_stride = 0;
     b->resident.assign(b->n, 0);
     b->units.assign(b->n, 0);
     b->part_begin.assign(b->n, 0);
@@ -314,6 +319,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
             b->part_begin[i] = (int32_t)tiles.size();
             for (int32_t c0 = 0; c0 < g.L; c0 += tw)
                 tiles.push_back({i, c0, std::min(tw, g.L - c0), (int32_t)tiles.size()});
+            if (tw < g.L) halo_stride = std::max(halo_stride, tile_halo_stride(g.N, p.tile_sweeps));
             b->part_count[i] = (int32_t)tiles.size() - b->part_begin[i];
             bool seen = false;
             for (const auto& gw : b->tile_shapes) seen = seen || (gw.first.L == g.L && gw.second == tw);
@@ -334,6 +340,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
     b->n_glb = (int32_t)ids_glb.size();
     b->n_tile_lat = (int32_t)ids_tile.size();
     b->n_tiles = (int32_t)tiles.size();
+    b->halo_stride = halo_stride;
     b->n_res_lat = (int32_t)ids_res.size();
     b->n_res = (int32_t)res_tiles.size();
     b->n_draw = (int32_t)ids_draw.size();
@@ -417,6 +424,7 @@ int apply_plan(ising_batch* b, const ising_batch_plan& p) {
         ISING_HIP(hipMalloc(&b->d_tiles, sizeof(TileWork) * tiles.size()));
         ISING_HIP(hipMemcpy(b->d_tiles, tiles.data(), sizeof(TileWork) * tiles.size(), hipMemcpyHostToDevice));
         ISING_HIP(hipMalloc(&b->d_tile_part, sizeof(Partial) * tiles.size() * kTileMaxSweeps));
+        if (halo_stride > 0) ISING_HIP(hipMalloc(&b->d_halo, sizeof(uint64_t) * tiles.size() * (size_t)halo_stride));
         ISING_HIP(hipMalloc(&b->d_ids_tile, sizeof(int32_t) * ids_tile.size()));
         ISING_HIP(hipMemcpy(b->d_ids_tile, ids_tile.data(), sizeof(int32_t) * ids_tile.size(), hipMemcpyHostToDevice));
     }
@@ -491,7 +499,7 @@ int enqueue_chunk(ising_batch* b, int32_t k, int32_t every, hipStream_t s0, hipS
         a.sample_mask = mask;
         a.n_tiles = b->n_tiles;
         a.partials = b->d_tile_part;
-        ISING_HIP(launch_tiles(a, b->n_tiles, p.tile_block, tile_launch_lds(b, kb), rs));
+        ISING_HIP(launch_tiles(a, b->n_tiles, p.tile_block, tile_launch_lds(b, kb), b->d_halo, b->halo_stride, rs));
         ISING_HIP(launch_finalize_tiles(b->d_desc, b->d_state, b->d_ids_tile, b->n_tile_lat, b->d_tile_part,
                                         b->n_tiles, mask, (uint32_t)done, rs));
         done += kb;

@@ -37,6 +37,8 @@ struct ising_lattice {
     TileWork* d_tiles = nullptr;
     LatticeDesc* d_desc = nullptr;  // words and geometry of this lattice for the tile kernel
     Partial* d_tpart = nullptr;     // kTileMaxSweeps x n_tiles partial sums
+    uint64_t* d_halo = nullptr;     // n_tiles x halo_stride: the tiles' halo copies (null: one tile)
+    int64_t halo_stride = 0;
     // resident tiles with boundary exchange (res_cols = 0: off)
     int res_cols = 0, res_block = 256, res_sweeps = 0;
     int32_t n_res = 0;
@@ -136,6 +138,7 @@ static void release(ising_lattice* h) {
     if (h->d_tiles) (void)hipFree(h->d_tiles);
     if (h->d_desc) (void)hipFree(h->d_desc);
     if (h->d_tpart) (void)hipFree(h->d_tpart);
+    if (h->d_halo) (void)hipFree(h->d_halo);
     if (h->d_res) (void)hipFree(h->d_res);
     if (h->d_exch) (void)hipFree(h->d_exch);
     if (h->d_flags) (void)hipFree(h->d_flags);
@@ -298,7 +301,7 @@ static int enqueue_tile_sweeps(const ising_lattice* h, uint64_t t0, double T, in
         a.K = kb;
         a.sample_mask = mask;
         ISING_HIP(launch_tiles(a, h->n_tiles, h->tile_block, tile_lds_bytes(h->g.L, h->g.N, h->tile_cols, kb),
-                               h->stream));
+                               h->d_halo, h->halo_stride, h->stream));
         if (n_samples)
             ISING_HIP(launch_finalize_samples(h->d_tpart, h->n_tiles, n_samples, h->g.L, dev_E, dev_M, first, mom,
                                               nullptr, h->stream));
@@ -646,8 +649,11 @@ int ising_set_tiling(ising_lattice* h, int32_t sweeps_per_launch, int32_t tile_c
     ISING_HIP(hipStreamSynchronize(h->stream));  // earlier launches may still read the old tables
     if (h->d_tiles) (void)hipFree(h->d_tiles);
     if (h->d_tpart) (void)hipFree(h->d_tpart);
+    if (h->d_halo) (void)hipFree(h->d_halo);
     h->d_tiles = nullptr;
     h->d_tpart = nullptr;
+    h->d_halo = nullptr;
+    h->halo_stride = 0;
     h->tile_k = 0;
     ISING_HIP(allow_tile_lds(h->device));
     free_resident(h);  // resident tiles off
@@ -656,6 +662,11 @@ int ising_set_tiling(ising_lattice* h, int32_t sweeps_per_launch, int32_t tile_c
     ISING_HIP(hipMalloc(&h->d_tiles, sizeof(TileWork) * tiles.size()));
     ISING_HIP(hipMemcpy(h->d_tiles, tiles.data(), sizeof(TileWork) * tiles.size(), hipMemcpyHostToDevice));
     ISING_HIP(hipMalloc(&h->d_tpart, sizeof(Partial) * tiles.size() * kTileMaxSweeps));
+    if (!whole) {
+        const int64_t stride = tile_halo_stride(N, K);
+        ISING_HIP(hipMalloc(&h->d_halo, sizeof(uint64_t) * tiles.size() * (size_t)stride));
+        h->halo_stride = stride;
+    }
     h->n_tiles = (int32_t)tiles.size();
     h->tile_k = K;
     h->tile_cols = w;

@@ -120,7 +120,16 @@ hipError_t launch_begin_call(LatticeState* states, int32_t n_lat, hipStream_t s)
 size_t tile_lds_bytes(int32_t L, int32_t N, int32_t w, int32_t K);
 size_t tile_lds_limit(int device);
 hipError_t allow_tile_lds(int device);
-hipError_t launch_tiles(const TileLaunch& a, int32_t n_tiles_launched, int block, size_t lds_bytes, hipStream_t s);
+// Words per tile of the halo copy for tiles of N word rows and launches of
+// up to K sweeps.
+int64_t tile_halo_stride(int32_t N, int32_t K);
+// A launch of the tiles a.tiles[0 .. n_tiles_launched): the halo columns of
+// the tiles narrower than their lattice are first copied into `halo`
+// (n_tiles_launched x halo_stride words, halo_stride at least
+// tile_halo_stride(N, a.K) for every such tile; 0 and null when every tile
+// holds a whole lattice), then the tiles run.
+hipError_t launch_tiles(const TileLaunch& a, int32_t n_tiles_launched, int block, size_t lds_bytes, uint64_t* halo,
+                        int64_t halo_stride, hipStream_t s);
 // The n_samples samples of one resident-tile launch of a batch (partials
 // [sample][tile], a lattice's tiles at part_begin .. + part_count) for the
 // listed lattices: series entries, moment sums, last E and M, in order.

@@ -19,6 +19,14 @@
 // A tile with w >= L holds the whole lattice: no halo, columns wrap inside
 // LDS, and any number of sweeps fits in one launch.
 //
+// The workgroups of a launch do not all start together (more tiles than fit
+// on the chip at once, or other work holding compute units), so a tile may
+// finish and store its interior before a neighbour has loaded it as halo.
+// The halo columns are therefore copied out of the lattice words by a small
+// kernel ahead of the tiles (k_tile_halos), and a tile loads its halo from
+// that copy and only its own interior from the lattice words, which no
+// other tile writes.
+//
 // All word rows of a column are in the tile, so the periodic wrap between
 // the first and last word rows, including the row-(L-1) patch, is resolved
 // inside LDS exactly as in the global-memory kernels (fix_up, fix_down).
@@ -60,14 +68,47 @@ struct TileCols {
     __device__ __forceinline__ int group_of_slot(int s) const { return s < A ? g_first + s : s - A; }
 };
 
+// Sweeps of a tile of lattice d in launch a (<= 0: the lattice has finished
+// the sweeps of its chunk).
+__device__ __forceinline__ int tile_sweeps_of(const TileLaunch& a, const LatticeDesc& d) {
+    return a.states ? min(a.K, d.sweep_limit - (int)a.sweep_off) : a.K;
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// The halo columns of every tile narrower than its lattice, as they stand
+// before the launch: tile b's words at H[b stride + (side N + I) R + k] for
+// word row I and k < R = 2K, side 0 the R columns left of the interior
+// (global columns c0 - R + k), side 1 the R columns right of it (c0 + w + k),
+// modulo L.  One workgroup per tile.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_tile_halos(TileLaunch a, uint64_t* __restrict__ H, int64_t stride) {
+    const TileWork tw = a.tiles[blockIdx.x];
+    const LatticeDesc& d = a.descs[tw.lattice];
+    const int L = d.L, N = d.N;
+    if (tw.w >= L) return;
+    const int K = tile_sweeps_of(a, d);
+    if (K <= 0) return;
+    const int R = 2 * K, NR = N * R;
+    const uint64_t* __restrict__ G = d.W;
+    uint64_t* __restrict__ Hb = H + (size_t)blockIdx.x * (size_t)stride;
+    for (int i = threadIdx.x; i < 2 * NR; i += blockDim.x) {
+        const int side = i >= NR ? 1 : 0, r = i - side * NR;
+        const int I = r / R, k = r - I * R;
+        int u = side ? tw.c0 + tw.w + k : tw.c0 - R + k;
+        u = u < 0 ? u + L : (u >= L ? u - L : u);
+        Hb[i] = G[(size_t)((uint32_t)I * (uint32_t)L + (uint32_t)u)];
+    }
+}
 
 // ---------------------------------------------------------------------------
 // One workgroup per tile.  LDS: the tile's words [N][width], then two tables
 // of position-20 blocks [slot][N] (uint4), the one read by the current
 // half-sweep and the one filled for the next.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kTileMaxBlock) k_tiles(TileLaunch a) {
+__global__ void __launch_bounds__(kTileMaxBlock) k_tiles(TileLaunch a, const uint64_t* __restrict__ H,
+                                                          int64_t stride) {
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t red[2 * (kTileMaxBlock / 64)];
     const TileWork tw = a.tiles[blockIdx.x];
@@ -83,7 +124,7 @@ __global__ void __launch_bounds__(kTileMaxBlock) k_tiles(TileLaunch a) {
         k1 = d.k1;
         t4 = d.t4;
         t8 = d.t8;
-        K = min(K, d.sweep_limit - (int)a.sweep_off);
+        K = tile_sweeps_of(a, d);
         if (K <= 0) return;  // this lattice has finished the sweeps of the chunk
     } else {
         t0 = a.t0;
@@ -108,11 +149,13 @@ __global__ void __launch_bounds__(kTileMaxBlock) k_tiles(TileLaunch a) {
     const uint64_t* __restrict__ G = d.W;
     const RoundKeys rk = round_keys(k0, k1);
 
-    // load the tile, eight loads in flight per thread
+    // load the tile, eight loads in flight per thread: the interior from the
+    // lattice words, the halo from the copy taken ahead of the launch
     {
         constexpr int kInFlight = 8;
         const float rcp = 1.0f / (float)width;
         const int n = N * width;
+        const uint64_t* __restrict__ Hb = H + (whole ? 0 : (size_t)blockIdx.x * (size_t)stride);
         for (int i0 = tid; i0 < n; i0 += kInFlight * B) {
             uint64_t v[kInFlight];
 #pragma unroll
@@ -121,7 +164,10 @@ __global__ void __launch_bounds__(kTileMaxBlock) k_tiles(TileLaunch a) {
                 if (i < n) {
                     int I, x;
                     divmod_small(i, width, rcp, I, x);
-                    v[k] = G[(size_t)((uint32_t)I * (uint32_t)L + (uint32_t)tc.col(x))];
+                    if (whole || (x >= R && x < R + tw.w))
+                        v[k] = G[(size_t)((uint32_t)I * (uint32_t)L + (uint32_t)tc.col(x))];
+                    else
+                        v[k] = Hb[(x < R ? I : N + I) * R + (x < R ? x : x - R - tw.w)];
                 }
             }
 #pragma unroll
@@ -326,10 +372,17 @@ hipError_t allow_tile_lds(int device) {
                                (int)tile_lds_limit(device));
 }
 
-hipError_t launch_tiles(const TileLaunch& a, int32_t n_tiles_launched, int block, size_t lds_bytes, hipStream_t s) {
+int64_t tile_halo_stride(int32_t N, int32_t K) { return 4 * (int64_t)K * (int64_t)N; }
+
+hipError_t launch_tiles(const TileLaunch& a, int32_t n_tiles_launched, int block, size_t lds_bytes, uint64_t* halo,
+                        int64_t halo_stride, hipStream_t s) {
     if (n_tiles_launched <= 0 || a.K <= 0) return hipSuccess;
     if (block < 64 || block > kTileMaxBlock || block % 64 || a.K > kTileMaxSweeps) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_tiles, dim3(n_tiles_launched), dim3(block), lds_bytes, s, a);
+    if (halo_stride > 0) {
+        if (!halo) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_tile_halos, dim3(n_tiles_launched), dim3(256), 0, s, a, halo, halo_stride);
+    }
+    hipLaunchKernelGGL(k_tiles, dim3(n_tiles_launched), dim3(block), lds_bytes, s, a, halo, halo_stride);
     return hipGetLastError();
 }
 

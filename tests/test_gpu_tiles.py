@@ -9,7 +9,8 @@ launch), halo tiles with 1 to 8 sweeps per launch, ragged last tiles, L not
 a multiple of 8 (position-20 groups split where the tile wraps past the
 lattice's end) or of 21 (the row-(L-1) patch), the paper's L = 21 N
 lattices, dead slots, sample counts that do not divide the sweeps per
-launch, and workgroups of 64 to 1024 threads.
+launch, workgroups of 64 to 1024 threads, and more tiles in one launch than
+the chip runs at once.
 """
 import numpy as np
 import pytest
@@ -114,6 +115,26 @@ def test_tiles_l4096_prefix_matches_oracle():
         lat.close()
     s = oracle.init(L, seed, True)
     Es, Ms = oracle.sweep(s, seed, 0, 30, T, every=10)
+    assert got_E == Es.tolist() and got_M == Ms.tolist()
+    assert (got == s).all()
+
+
+def test_tiles_more_than_fit_at_once_match_oracle():
+    """2048 two-column tiles of L = 4096 in one launch: more workgroups than
+    the chip holds at once, so tiles of a later round load their halos after
+    their neighbours have stored their interiors (the halos come from the
+    copy taken ahead of the launch)."""
+    L, seed, T = 4096, 19, 2.269
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        lat.set_tiling(1, 2, 64)
+        E, M = lat.sweep_measure(T, 6, 2)
+        got = lat.spins()
+        got_E, got_M = E.cpu().numpy().tolist(), M.cpu().numpy().tolist()
+    finally:
+        lat.close()
+    s = oracle.init(L, seed, True)
+    Es, Ms = oracle.sweep(s, seed, 0, 6, T, every=2)
     assert got_E == Es.tolist() and got_M == Ms.tolist()
     assert (got == s).all()
 
