@@ -270,7 +270,11 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
     // a long scalar routine)
     int64_t next_sample = a.every > 0 ? (int64_t)a.every - 1 - a.sample_base % a.every : -1;
     int n_taken = 0;
-    for (int hs = 0; hs < n_hs; ++hs) {
+    // one half-sweep: the word items of its colour (cur0, cur1) and of the
+    // other colour (oth0, oth1), whose codes it draws for the next one;
+    // returns whether the launch stops
+    auto half_sweep = [&](const int hs, const WordItem& cur0, const WordItem& cur1, const WordItem& oth0,
+                          const WordItem& oth1) __attribute__((always_inline)) -> bool {
         const int c = hs & 1;
         const int j = hs >> 1;
         const LdsSweep sw = sweep_of(hs);
@@ -401,14 +405,18 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
             next_sample += a.every;
             ++n_taken;
         }
-        if (stop) break;
-        if (pre) {  // the next half-sweep has the other colour
-            const WordItem t0i = cur0, t1i = cur1;
-            cur0 = oth0;
-            cur1 = oth1;
-            oth0 = t0i;
-            oth1 = t1i;
+        return stop != 0;
+    };
+    if (pre) {
+        // two half-sweeps per trip, so that the items of each colour stay in
+        // the same registers (no exchange of the two sets between half-sweeps)
+        for (int hs = 0; hs < n_hs; hs += 2) {
+            if (half_sweep(hs, cur0, cur1, oth0, oth1)) break;
+            if (half_sweep(hs + 1, oth0, oth1, cur0, cur1)) break;
         }
+    } else {
+        for (int hs = 0; hs < n_hs; ++hs)
+            if (half_sweep(hs, cur0, cur1, oth0, oth1)) break;
     }
     // the ghost columns in LDS are stale past the first half-sweep, but the
     // band's own words are exact
