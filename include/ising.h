@@ -291,9 +291,9 @@ int ising_get_tiling(ising_lattice* h, int32_t* sweeps_per_launch, int32_t* tile
    about a second is abandoned: the next call on the handle returns
    ISING_EHIP, and the lattice state is undefined.  Synchronises.  Results
    never depend on it.  ising_get_resident_tiles returns zeros when off.
-   ising_create and ising_create_in switch it on for 2560 <= L <= 4608
-   (bands of 2 ceil(L / 512) columns, 1024 threads, 1000 sweeps per launch)
-   when those fit. */
+   ising_create and ising_create_in switch it on for 512 <= L <= 7680
+   (bands of 2 ceil(L / 512) columns, 1024 threads (512 below L = 1024),
+   1000 sweeps per launch) when those fit. */
 int ising_set_resident_tiles(ising_lattice* h, int32_t tile_cols, int32_t block, int32_t max_sweeps);
 /* Bound of every wait of the resident-tile launches for their neighbour
    tiles, in ticks of the GPU's 100 MHz constant clock; 0 restores the

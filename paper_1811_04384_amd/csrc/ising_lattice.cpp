@@ -207,14 +207,17 @@ static int create_impl(int32_t L, uint64_t seed, int32_t init, void* dev_words, 
         release(h);
         return hip_fail(e, "init kernel launch");
     }
-    // From about 2560 to 4608 columns (N up to 220 word rows) resident tiles
-    // are faster (measured at L = 4096: 1450 against 1108 attempts/ns): bands
-    // of about L/256 columns, one 1024-thread workgroup each, so that every
-    // compute unit holds one; smaller lattices leave compute units idle with
-    // either path and larger ones do not fit.
-    if (L >= 2560 && L <= 4608) {
+    // From 512 to 7680 columns resident tiles are faster than one launch per
+    // half-sweep at every size measured (attempts/ns, resident against
+    // half-sweep launches: L = 512 47 / 31, 1024 181 / 152, 2048 743 / 525,
+    // 4096 2182 / 1120, 5120 1687 / 1311, 7680 1815 / 1611): bands of about
+    // L/256 columns, one workgroup each (1024 threads, 512 below L = 1024),
+    // so that every compute unit holds one.  Above 7680 a band no longer
+    // fits in LDS; where the tiles do not fit the lattice keeps the
+    // half-sweep launches.
+    if (L >= 512 && L <= 7680) {
         const int32_t w = 2 * ((L + 511) / 512);
-        if (ising_set_resident_tiles(h, w, 1024, 1000) != ISING_OK) last_error_ref().clear();
+        if (ising_set_resident_tiles(h, w, L < 1024 ? 512 : 1024, 1000) != ISING_OK) last_error_ref().clear();
     }
     *out = h;
     return ISING_OK;

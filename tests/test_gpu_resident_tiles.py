@@ -8,8 +8,9 @@ oracle's.  Cases: the whole lattice in one workgroup (no exchange), many
 bands, two bands (each the other's left and right neighbour), ragged last
 bands down to two columns, L not a multiple of 8 or of 21, the paper's
 L = 21 N lattices, samples spanning launches (calls longer than one launch),
-workgroups of 64 to 1024 threads, and both ways of drawing the codes (per
-word item in its half-sweep, or a half-sweep ahead into LDS code tables).
+workgroups of 64 to 1024 threads, both ways of drawing the codes (per
+word item in its half-sweep, or a half-sweep ahead into LDS code tables),
+and the library's default shapes from L = 512 to 7680.
 """
 import pytest
 
@@ -123,6 +124,40 @@ def test_resident_tiles_l4096_prefix_matches_oracle():
     Es, Ms = oracle.sweep(s, seed, 0, 30, T, every=10)
     assert got_E == Es.tolist() and got_M == Ms.tolist()
     assert (got == s).all()
+
+
+@pytest.mark.parametrize("L,tiles", [(512, (2, 512, 1000)), (770, (4, 512, 1000)), (2304, (10, 1024, 1000)),
+                                     (5000, (20, 1024, 1000)), (7680, (30, 1024, 1000))])
+def test_default_resident_tiles_match_oracle(L, tiles):
+    """The library's default for 512 <= L <= 7680 (bands of about L/256
+    columns, all resident at once): the default is taken, and series and
+    state equal the oracle's (ragged last band at L = 770, two-column bands
+    at L = 512, the largest band that fits at L = 7680)."""
+    seed, T = 3 + L, 2.269
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        assert lat.resident_tiles() == tiles
+        print(f"default resident tiles L={L} {tiles}", flush=True)
+        E, M = lat.sweep_measure(T, 7, 2)
+        got = lat.spins()
+        got_E, got_M = E.cpu().numpy().tolist(), M.cpu().numpy().tolist()
+    finally:
+        lat.close()
+    s = oracle.init(L, seed, True)
+    Es, Ms = oracle.sweep(s, seed, 0, 7, T, every=2)
+    assert got_E == Es.tolist() and got_M == Ms.tolist()
+    assert (got == s).all()
+
+
+def test_default_plan_outside_the_resident_range():
+    """Below 512 and above 7680 columns the default stays one launch per
+    half-sweep."""
+    for L in (510, 7682):
+        lat = ising.Lattice(L, 1, hot=False)
+        try:
+            assert lat.resident_tiles() == (0, 0, 0), L
+        finally:
+            lat.close()
 
 
 def test_invalid_resident_tiles_are_rejected():

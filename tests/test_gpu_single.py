@@ -91,6 +91,7 @@ def test_every_plan_gives_identical_results(L):
         for block in (64, 128, 256):
             lat = ising.Lattice(L, seed, hot=True)
             try:
+                lat.set_resident_tiles(0)  # the half-sweep launches, whatever the default for L
                 lat.set_plan(wpt, block)
                 lat.sweep(T, n)
                 assert (lat.spins() == s_ref).all(), (wpt, block)
