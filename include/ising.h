@@ -289,8 +289,10 @@ int ising_get_tiling(ising_lattice* h, int32_t* sweeps_per_launch, int32_t* tile
    EINVAL if a tile does not fit in LDS or the tiles do not all fit on the
    device at once.  A launch whose tiles wait for a neighbour longer than
    about a second is abandoned: the next call on the handle returns
-   ISING_EHIP, and the lattice state is undefined.  Synchronises.  Results
-   never depend on it.  ising_get_resident_tiles returns zeros when off.
+   ISING_EHIP, and the lattice state is undefined.  Launches of resident
+   tiles on different streams of one device (of this or other handles and
+   batches) run one after another.  Synchronises.  Results never depend on
+   it.  ising_get_resident_tiles returns zeros when off.
    ising_create and ising_create_in switch it on for 512 <= L <= 7680
    (bands of 2 ceil(L / 512) columns, 1024 threads (512 below L = 1024),
    1000 sweeps per launch) when those fit. */

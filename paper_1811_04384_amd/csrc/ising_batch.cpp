@@ -572,7 +572,10 @@ int sweep_impl(ising_batch* b, const double* T, int64_t n, int32_t every, int64_
         hipGraphExec_t g = nullptr;
         rc = get_graph(b, k, every, &g);
         if (rc != ISING_OK) return rc;
-        ISING_HIP(hipGraphLaunch(g, b->stream));
+        if (b->n_res > 0)  // the chunk holds resident tiles
+            ISING_HIP(resident_gate(b->device, b->stream, [&] { return hipGraphLaunch(g, b->stream); }));
+        else
+            ISING_HIP(hipGraphLaunch(g, b->stream));
         done += k;
     }
     for (auto& t : b->t_host) t += (uint64_t)n;

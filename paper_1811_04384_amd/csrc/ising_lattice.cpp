@@ -354,7 +354,8 @@ static int enqueue_resident_sweeps(ising_lattice* h, uint64_t t0, double T, int6
         a.t0 = t0 + (uint64_t)done;
         a.K = kb;
         a.sample_base = done;
-        ISING_HIP(launch_persist(a, h->n_res, h->res_block, h->res_lds, h->stream));
+        ISING_HIP(resident_gate(h->device, h->stream,
+                                [&] { return launch_persist(a, h->n_res, h->res_block, h->res_lds, h->stream); }));
         const int64_t n_samples = every > 0 ? (done + kb) / every - done / every : 0;
         if (n_samples > 0) {
             const int64_t idx0 = done / every;  // series index of the launch's first sample

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "ising_common.hpp"
 
 namespace ising {
@@ -162,6 +164,12 @@ hipError_t allow_persist_lds(int device);
 // holds at once (a launch must not exceed it).
 hipError_t persist_capacity(int block, size_t lds_bytes, int device, int64_t* tiles);
 hipError_t launch_persist(const PersistLaunch& a, int32_t n_tiles, int block, size_t lds_bytes, hipStream_t s);
+// Runs launch(), which enqueues work holding resident tiles on stream s of
+// `device`, ordered after the previous such work of this process on that
+// device (a stream wait on its completion event), and makes it the previous
+// one.  Inside a graph capture of s, or with another device current,
+// launch() runs unordered.
+hipError_t resident_gate(int device, hipStream_t s, const std::function<hipError_t()>& launch);
 // The n_samples samples of one resident-tile launch of a batch (partials
 // [sample][tile], a lattice's tiles at part_begin .. + part_count) for the
 // listed lattices: series entries, moment sums, last E and M, in order.

@@ -41,6 +41,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "ising_device.hpp"
 #include "ising_launch.hpp"
@@ -479,6 +481,39 @@ hipError_t launch_persist(const PersistLaunch& a, int32_t n_tiles, int block, si
     if (block < 64 || block > kPersistMaxBlock || block % 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_persist, dim3(n_tiles), dim3(block), lds_bytes, s, a);
     return hipGetLastError();
+}
+
+// The completion of the last launch that holds resident tiles, per device
+// (null until the first one).  Two such launches on different streams could
+// each hold compute units that the other's remaining workgroups need, and
+// both would then wait out their bound and fail; ordering every one after
+// the device's previous one rules that out.
+namespace {
+std::mutex g_gate_mutex;
+std::vector<hipEvent_t> g_gate;
+}  // namespace
+
+hipError_t resident_gate(int device, hipStream_t s, const std::function<hipError_t()>& launch) {
+    std::lock_guard<std::mutex> lock(g_gate_mutex);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return e;
+    int current = -1;
+    e = hipGetDevice(&current);
+    if (e != hipSuccess) return e;
+    // inside a capture a dependency on work outside it is not allowed, and
+    // the event belongs to the device current when it was made
+    if (cs != hipStreamCaptureStatusNone || device < 0 || current != device) return launch();
+    if ((size_t)device >= g_gate.size()) g_gate.resize((size_t)device + 1, nullptr);
+    if (g_gate[device]) {
+        e = hipStreamWaitEvent(s, g_gate[device], 0);
+    } else {
+        e = hipEventCreateWithFlags(&g_gate[device], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    return hipEventRecord(g_gate[device], s);
 }
 
 }  // namespace ising

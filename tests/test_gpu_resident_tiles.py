@@ -149,6 +149,43 @@ def test_default_resident_tiles_match_oracle(L, tiles):
     assert (got == s).all()
 
 
+def test_resident_launches_on_two_streams():
+    """Two lattices in the default resident tiles (256 bands of 1024 threads
+    each, one per compute unit) on two streams, every call made with its own
+    stream current so that nothing but the library orders them: each
+    launch runs after the device's previous resident launch, so neither
+    waits out its bound on tiles the other holds, and both equal the
+    oracle."""
+    import torch
+
+    L, T = 2048, 2.269
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    lats = [ising.Lattice(L, 50 + k, hot=True, stream=streams[k]) for k in range(2)]
+    try:
+        assert all(lat.resident_tiles() == (8, 1024, 1000) for lat in lats)
+        print("resident tiles on two streams", flush=True)
+        for _ in range(3):
+            for k in range(2):
+                with torch.cuda.stream(streams[k]):
+                    lats[k].sweep(T, 40)
+        series = []
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                series.append(lats[k].sweep_measure(T, 20, 5))
+        torch.cuda.synchronize()
+        for k in range(2):
+            lats[k].synchronize()
+            s = oracle.init(L, 50 + k, True)
+            oracle.sweep(s, 50 + k, 0, 120, T)
+            Es, Ms = oracle.sweep(s, 50 + k, 120, 20, T, every=5)
+            E, M = series[k]
+            assert E.cpu().numpy().tolist() == Es.tolist() and M.cpu().numpy().tolist() == Ms.tolist(), k
+            assert (lats[k].spins() == s).all(), k
+    finally:
+        for lat in lats:
+            lat.close()
+
+
 def test_default_plan_outside_the_resident_range():
     """Below 512 and above 7680 columns the default stays one launch per
     half-sweep."""
