@@ -293,9 +293,11 @@ int ising_get_tiling(ising_lattice* h, int32_t* sweeps_per_launch, int32_t* tile
    tiles on different streams of one device (of this or other handles and
    batches) run one after another.  Synchronises.  Results never depend on
    it.  ising_get_resident_tiles returns zeros when off.
-   ising_create and ising_create_in switch it on for 512 <= L <= 7680
-   (bands of 2 ceil(L / 512) columns, 1024 threads (512 below L = 1024),
-   1000 sweeps per launch) when those fit. */
+   ising_create and ising_create_in switch it on for L <= 7680 (up to
+   L = 192 the whole lattice in one workgroup of one thread per word of a
+   colour, a power of two from 64 to 1024; below L = 1024 bands of 8
+   columns, 512 threads; from there bands of 2 ceil(L / 512) columns, 1024
+   threads; 1000 sweeps per launch) when those fit. */
 int ising_set_resident_tiles(ising_lattice* h, int32_t tile_cols, int32_t block, int32_t max_sweeps);
 /* Bound of every wait of the resident-tile launches for their neighbour
    tiles, in ticks of the GPU's 100 MHz constant clock; 0 restores the

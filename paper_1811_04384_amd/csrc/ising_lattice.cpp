@@ -207,17 +207,29 @@ static int create_impl(int32_t L, uint64_t seed, int32_t init, void* dev_words, 
         release(h);
         return hip_fail(e, "init kernel launch");
     }
-    // From 512 to 7680 columns resident tiles are faster than one launch per
+    // Up to 7680 columns resident tiles are faster than one launch per
     // half-sweep at every size measured (attempts/ns, resident against
-    // half-sweep launches: L = 512 47 / 31, 1024 181 / 152, 2048 743 / 525,
-    // 4096 2182 / 1120, 5120 1687 / 1311, 7680 1815 / 1611): bands of about
-    // L/256 columns, one workgroup each (1024 threads, 512 below L = 1024),
-    // so that every compute unit holds one.  Above 7680 a band no longer
-    // fits in LDS; where the tiles do not fit the lattice keeps the
-    // half-sweep launches.
-    if (L >= 512 && L <= 7680) {
-        const int32_t w = 2 * ((L + 511) / 512);
-        if (ising_set_resident_tiles(h, w, L < 1024 ? 512 : 1024, 1000) != ISING_OK) last_error_ref().clear();
+    // half-sweep launches, E/M every 10 sweeps: L = 64 1.7 / 0.7, 128
+    // 5.2 / 2.9, 256 11.6 / 10.2, 512 47.6 / 45.0, 1024 190 / 152, 2048
+    // 743 / 525, 4096 2182 / 1120, 5120 1687 / 1311, 7680 1815 / 1611).
+    // Shapes: up to L = 192 the whole lattice in one workgroup, a thread per
+    // word of a colour (a power of two, 64 to 1024); below L = 1024 bands
+    // of 8 columns, 512 threads; from there bands of 2 ceil(L / 512)
+    // columns (at most 256, one per compute unit), 1024 threads.  Above
+    // 7680 a band no longer fits in LDS; where the tiles do not fit the
+    // lattice keeps the half-sweep launches.
+    if (L <= 7680) {
+        int32_t w = 2 * ((L + 511) / 512), block = 1024;
+        if (L <= 192) {
+            const int64_t items = (int64_t)h->g.N * L / 2;
+            w = L;
+            block = 64;
+            while (block < 1024 && block < items) block *= 2;
+        } else if (L < 1024) {
+            w = 8;
+            block = 512;
+        }
+        if (ising_set_resident_tiles(h, w, block, 1000) != ISING_OK) last_error_ref().clear();
     }
     *out = h;
     return ISING_OK;

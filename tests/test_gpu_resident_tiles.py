@@ -10,7 +10,7 @@ bands down to two columns, L not a multiple of 8 or of 21, the paper's
 L = 21 N lattices, samples spanning launches (calls longer than one launch),
 workgroups of 64 to 1024 threads, both ways of drawing the codes (per
 word item in its half-sweep, or a half-sweep ahead into LDS code tables),
-and the library's default shapes from L = 512 to 7680.
+and the library's default shapes from L = 4 to 7680.
 """
 import pytest
 
@@ -126,13 +126,16 @@ def test_resident_tiles_l4096_prefix_matches_oracle():
     assert (got == s).all()
 
 
-@pytest.mark.parametrize("L,tiles", [(512, (2, 512, 1000)), (770, (4, 512, 1000)), (2304, (10, 1024, 1000)),
+@pytest.mark.parametrize("L,tiles", [(4, (4, 64, 1000)), (64, (64, 128, 1000)), (130, (130, 1024, 1000)),
+                                     (192, (192, 1024, 1000)), (194, (8, 512, 1000)), (512, (8, 512, 1000)),
+                                     (770, (8, 512, 1000)), (1024, (4, 1024, 1000)), (2304, (10, 1024, 1000)),
                                      (5000, (20, 1024, 1000)), (7680, (30, 1024, 1000))])
 def test_default_resident_tiles_match_oracle(L, tiles):
-    """The library's default for 512 <= L <= 7680 (bands of about L/256
-    columns, all resident at once): the default is taken, and series and
-    state equal the oracle's (ragged last band at L = 770, two-column bands
-    at L = 512, the largest band that fits at L = 7680)."""
+    """The library's default up to L = 7680 (the whole lattice in one
+    workgroup up to L = 192, then bands of 8 columns, then bands of about
+    L/256 columns, all resident at once): the default is taken, and series
+    and state equal the oracle's (ragged last bands at L = 194 and 770, the
+    largest band that fits at L = 7680)."""
     seed, T = 3 + L, 2.269
     lat = ising.Lattice(L, seed, hot=True)
     try:
@@ -187,9 +190,8 @@ def test_resident_launches_on_two_streams():
 
 
 def test_default_plan_outside_the_resident_range():
-    """Below 512 and above 7680 columns the default stays one launch per
-    half-sweep."""
-    for L in (510, 7682):
+    """Above 7680 columns the default stays one launch per half-sweep."""
+    for L in (7682, 8192):
         lat = ising.Lattice(L, 1, hot=False)
         try:
             assert lat.resident_tiles() == (0, 0, 0), L
