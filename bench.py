@@ -350,10 +350,11 @@ def run_batched(ising, sweeps=5000, every=10, autotune=True, plain=True):
 
 def run_batched_as_plain(ising, Ls, Ts, seeds, sweeps=2000, every=10):
     """The batched mix run the plain way, one lattice per launch and one
-    lattice after another, on a sample: lattices 0..3 of the mix (one of each
-    size, with their seeds and temperatures), 2000 sweeps each with E/M every
-    10 (about 60 ms).  The mix holds the four sizes in equal numbers, so the
-    sample's rate is the mix's rate."""
+    lattice after another, each in the single-lattice default plan for its
+    size (resident tiles for all four sizes), on a sample: lattices 0..3 of
+    the mix (one of each size, with their seeds and temperatures), 2000
+    sweeps each with E/M every 10 (about 60 ms).  The mix holds the four
+    sizes in equal numbers, so the sample's rate is the mix's rate."""
     import torch
 
     lats = [ising.Lattice(Ls[i], seeds[i], hot=True) for i in range(4)]
@@ -377,7 +378,9 @@ def run_batched_as_plain(ising, Ls, Ts, seeds, sweeps=2000, every=10):
 def run_scan64(ising, therm=2000, meas=2000, plain=True):
     """L=64, cold start, 8 temperatures over [1.5, 3.5], seed 1234, 2000 + 2000
     sweeps (sample every measured sweep): batched (codes drawn chip-wide, one
-    workgroup per lattice applying them in LDS) and as 8 plain lattices."""
+    workgroup per lattice applying them in LDS) and as 8 plain lattices one
+    after another, each in the single-lattice default plan (the whole lattice
+    in one workgroup, resident in LDS for up to 1000 sweeps per launch)."""
     import torch
 
     Ts = [1.5 + 2.0 * i / 7 for i in range(8)]
