@@ -53,6 +53,10 @@ CASES = [
     # most two (its code tables must fit the LDS reserved for the wide ones)
     (1008, 23, True, 22, 256, 3),
     (1010, 24, False, 32, 256, 4),
+    # a partial last round of second items (more words of a colour than
+    # threads, not a multiple of 64 more) with 256 and 512 threads
+    (200, 31, True, 60, 256, 5),
+    (500, 32, False, 50, 512, 6),
 ]
 
 
