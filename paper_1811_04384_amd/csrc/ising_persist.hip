@@ -366,8 +366,17 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
             }
         }
         if (meas) {
-            anti = wave_sum_u32(anti);
-            ups = wave_sum_u32(ups);
+            if (pre) {
+                // at most two words per thread: a wavefront's antiparallel
+                // bonds (at most 168 per thread) and up spins (84) each fit
+                // in 16 bits, so one sum covers both
+                const uint32_t both = wave_sum_u32((anti << 16) | ups);
+                anti = both >> 16;
+                ups = both & 0xFFFFu;
+            } else {
+                anti = wave_sum_u32(anti);
+                ups = wave_sum_u32(ups);
+            }
             if (lane_id() == 0) {
                 red[2 * (tid >> 6)] = anti;
                 red[2 * (tid >> 6) + 1] = ups;
@@ -395,13 +404,13 @@ __global__ void __launch_bounds__(kPersistMaxBlock) k_persist(PersistLaunch a) {
             if (!ok) stop = 1;
         }
         __syncthreads();
-        if (meas && tid == 0) {
-            uint32_t sa = 0, su = 0;
-            for (int wv = 0; wv < (B + 63) / 64; ++wv) {
-                sa += red[2 * wv];
-                su += red[2 * wv + 1];
-            }
-            a.partials[(size_t)n_taken * a.n_tiles + tp.part] = {sa, su};
+        if (meas && tid >= B - 64) {
+            // the tile's sums, by the last wavefront: lane l reads
+            // wavefront l's pair, one sum over the lanes for each count
+            const int l = tid - (B - 64);
+            const bool in = l < (B >> 6);
+            const uint32_t sa = wave_sum_u32(in ? red[2 * l] : 0u), su = wave_sum_u32(in ? red[2 * l + 1] : 0u);
+            if (l == 0) a.partials[(size_t)n_taken * a.n_tiles + tp.part] = {sa, su};
         }
         if (meas) {
             next_sample += a.every;
