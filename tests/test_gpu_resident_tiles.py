@@ -203,6 +203,28 @@ def test_default_plan_outside_the_resident_range():
             lat.close()
 
 
+def test_default_resident_tiles_l4096_full_launch_matches_oracle():
+    """The single-lattice workload in the launch configuration the benchmark
+    times: L = 4096, hot start seed 7, T = 2.269, the default plan (256
+    bands of 16 columns, 1024 threads, 1000 sweeps per launch), one whole
+    launch of 1000 sweeps with E/M every 10 sweeps: all 100 samples and the
+    final state equal the oracle's (about 20 s of oracle work)."""
+    L, seed, T = 4096, 7, 2.269
+    lat = ising.Lattice(L, seed, hot=True)
+    try:
+        assert lat.resident_tiles() == (16, 1024, 1000)
+        print("L=4096 default plan, one 1000-sweep launch", flush=True)
+        E, M = lat.sweep_measure(T, 1000, 10)
+        got = lat.spins()
+        got_E, got_M = E.cpu().numpy().tolist(), M.cpu().numpy().tolist()
+    finally:
+        lat.close()
+    s = oracle.init(L, seed, True)
+    Es, Ms = oracle.sweep(s, seed, 0, 1000, T, every=10)
+    assert got_E == Es.tolist() and got_M == Ms.tolist()
+    assert (got == s).all()
+
+
 def test_invalid_resident_tiles_are_rejected():
     lat = ising.Lattice(4096, 1, hot=True)
     try:
