@@ -115,6 +115,29 @@ def test_batch_scan_matches_oracle(plan):
     b.close()
 
 
+def test_heating_workload_plan_matches_oracle():
+    """The heating workload's shape and plan as the benchmark runs it: 16 x
+    L = 1008, cold, seeds 0..15, resident tiles of 64 columns on 1024
+    threads, 200 sweeps per chunk, carried over two temperatures with 40
+    unsampled and 220 sampled sweeps each (so a chunk boundary falls inside
+    the sampled run): every lattice's moment sums, state and sweep count
+    equal the oracle's (about 10 s of oracle work)."""
+    Ts = [1.5, 2.3]
+    n = 16
+    b = ising.Batch([1008] * n, list(range(n)), hot=False)
+    try:
+        b.set_plan(resident_max_L=0, resident_block=256, words_per_thread=1, tiled_block=64, sweeps_per_graph=200,
+                   tile_max_L=1008, tile_sweeps=1, tile_cols=64, tile_block=1024, tile_exchange=1)
+        print("heating workload plan, 16 x L=1008", flush=True)
+        got = b.scan(Ts, 40, 220, 1)
+        for i in range(n):
+            want, s, t = oracle.scan(1008, i, False, Ts, 40, 220, 1)
+            assert [got[j][i] for j in range(2)] == want, i
+            assert np.array_equal(b.spins(i), s) and b.sweep_count(i) == t
+    finally:
+        b.close()
+
+
 def test_gpu_heating_scan_specific_heat_matches_kaufman():
     """Eight replicas of a 32 x 32 torus heated through the transition on the
     GPU: the replica-averaged energy and specific heat per spin at each
